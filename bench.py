@@ -1,0 +1,146 @@
+"""Benchmark: correctly rounded Gelem/s and % of the HBM roofline on one MI355X.
+
+One step = one pass of the hot path over the exp/log-family workload: each of
+expf, exp2f, exp10f, expm1f, logf, log2f, log10f, log1pf, rsqrtf evaluated on
+its own 2^26 binary32 inputs (90% uniform over the domain, 5% raw bit
+patterns, 5% hard-to-round inputs; paper_2605_15547_amd/inputs.py), inputs
+resident in HBM before the timed region.  Functions the library does not
+provide yet are listed in config.missing and left out.
+
+Output: one JSON line.  value = total elements / total time (Gelem/s).  The
+roofline object describes the kernel with the largest share of the step:
+algorithmic bytes (4 B in + 4 B out per element) over its average launch
+time, measured with HIP events on the stream it runs on.  cpu_baseline times
+the CPU oracle (oracle/) on a bounded sample of the same inputs.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n LOG2N]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FAMILY = ["expf", "exp2f", "exp10f", "expm1f", "logf", "log2f", "log10f", "log1pf", "rsqrtf"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=26, help="log2 of elements per function")
+    ap.add_argument("--impl", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: the method is an elementwise map with no "
+              "exchange between GPUs, and this build runs on a single MI355X.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_15547_amd import crmath, inputs
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    crmath.lib()
+    dev = torch.device("cuda:0")
+    n = 1 << a.n
+    funcs = [f for f in FAMILY if crmath.available(f, a.impl)]
+    missing = [f for f in FAMILY if f not in funcs]
+    log("bench: functions", funcs, "missing", missing, "n", n)
+
+    xs, outs, host = {}, {}, {}
+    for f in funcs:
+        t0 = time.time()
+        x = inputs.workload_f32(f, n)
+        host[f] = x
+        xs[f] = torch.from_numpy(x).to(dev)
+        outs[f] = torch.empty_like(xs[f])
+        log("bench: generated %s in %.1fs" % (f, time.time() - t0))
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    sp = crmath._stream_ptr(stream)
+
+    def run(f):
+        crmath.eval_ptr(f, xs[f].data_ptr(), outs[f].data_ptr(), n, a.impl, 0, sp)
+
+    for _ in range(a.warmup):
+        for f in funcs:
+            run(f)
+    torch.cuda.synchronize()
+    crmath.stats_reset()
+
+    # per-function events on the launch stream
+    ev = {f: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(a.steps)] for f in funcs}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        for f in funcs:
+            ev[f][s][0].record(stream)
+            run(f)
+            ev[f][s][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = crmath.stats_read()
+
+    per = {}
+    for f in funcs:
+        ms = float(np.mean([b.elapsed_time(e) for b, e in ev[f]]))
+        gbs = 8.0 * n / (ms * 1e-3) / 1e9
+        per[f] = {"ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                  "gb_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    total_elems = n * len(funcs) * a.steps
+    value = total_elems / wall / 1e9
+    dom = max(funcs, key=lambda f: per[f]["ms"])
+    roof = {"bound": "hbm", "kernel": "k_map_f32_vec<%s>" % dom,
+            "achieved": per[dom]["gb_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(per[dom]["gb_s"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_elem": 8, "elems_per_launch": n}
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        from oracle import oracle as O
+        O.build()
+        threads = O.default_threads()
+        m = 1 << 13
+        t0 = time.perf_counter()
+        cnt = 0
+        for f in funcs:
+            O.evaluate(f, host[f][:m], threads)
+            cnt += m
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(cnt / dt / 1e9, 6), "unit": "Gelem/s", "cores": threads,
+               "kind": "oracle",
+               "sample": "first %d inputs of each function's workload (%d elements), "
+                         "Ziv loop over fixed-point ball arithmetic, %.1f s" % (m, cnt, dt)}
+
+    rec = {"metric": "correctly rounded Gelem/s (exp/log family, binary32), bit-exact",
+           "value": round(value, 2), "unit": "Gelem/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": round(wall / a.steps * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 (binary32 in/out)", "data": "synthetic",
+           "config": {"workload": "exp/log family, 2^%d binary32 inputs per function" % a.n,
+                      "functions": funcs, "missing": missing, "elems_per_function": n,
+                      "impl": "f64_internal" if a.impl in (0, 1) else "split_f32"},
+           "per_func": per,
+           "fallback": {"lanes": st["fallback_lanes"], "waves": st["fallback_waves"],
+                        "escapes": st["escapes"],
+                        "lane_rate": st["fallback_lanes"] / max(1, total_elems)},
+           "roofline": roof, "cpu_baseline": cpu}
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

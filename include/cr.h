@@ -1,0 +1,127 @@
+/*
+ * cr.h -- correctly rounded elementwise math on AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates one-input functions correctly rounded to nearest
+ * (ties to even), element by element, on the GPU: the 19 single precision
+ * functions the paper lists (Sec. II-A: acosf, asinf, atanf, cosf, coshf,
+ * expf, exp2f, exp10f, expm1f, log10f, log1pf, log2f, logf, sincosf, sinf,
+ * sinhf, rsqrtf, tanf, tanhf) and double precision exp and log (the paper
+ * studies double precision exp2 and log in Sec. II-B; this library provides
+ * exp and log).  "Correctly rounded" means the result is RN(f(x)) for the
+ * exact real f(x) (paper, Sec. I).  Only round-to-nearest-even is provided,
+ * as in the paper's GPU experiments (Sec. III-C).
+ *
+ * Conventions shared by every entry point:
+ *  - in/out are DEVICE pointers owned by the caller, on the current HIP
+ *    device; the stream argument is a hipStream_t (NULL = default stream).
+ *  - element type follows func_id: float for ids 0..18, double for 64, 65;
+ *    n counts input elements.  sincosf writes 2n floats, planar:
+ *    out[0..n) = sin(in), out[n..2n) = cos(in).
+ *  - n == 0 returns CR_OK without launching anything.
+ *  - in == out (in place) is allowed for single-output functions; any other
+ *    overlap of the input and output ranges is CR_E_OVERLAP.
+ *  - pointers must be aligned to their element size (CR_E_ALIGN); 16-byte
+ *    alignment is not required.
+ *  - calls are asynchronous and stream-ordered: the return code reports
+ *    argument and launch errors only; device faults surface at stream
+ *    synchronisation as usual in HIP.  Entry points never abort or set errno.
+ *  - special inputs follow IEEE 754-2019 Sec. 9.2: NaN inputs return the same
+ *    NaN quieted (sign and payload kept); invalid operations on non-NaN
+ *    inputs return the default quiet NaN 0x7fc00000 / 0x7ff8000000000000.
+ *    Subnormal inputs and outputs are fully supported (no flush to zero).
+ *  - no floating-point status flags are raised (the paper's SIMD libraries
+ *    do not aim to set them either, Sec. II-A).
+ */
+#ifndef CR_H
+#define CR_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum cr_func {
+  CR_EXPF = 0, CR_EXP2F = 1, CR_EXP10F = 2, CR_EXPM1F = 3,
+  CR_LOGF = 4, CR_LOG2F = 5, CR_LOG10F = 6, CR_LOG1PF = 7,
+  CR_RSQRTF = 8,
+  CR_SINF = 9, CR_COSF = 10, CR_SINCOSF = 11, CR_TANF = 12,
+  CR_ASINF = 13, CR_ACOSF = 14, CR_ATANF = 15,
+  CR_SINHF = 16, CR_COSHF = 17, CR_TANHF = 18,
+  CR_NUM_F32 = 19,
+  CR_EXP = 64, CR_LOG = 65 /* binary64 */
+};
+
+/* Implementation choice for the binary32 functions (paper, Sec. II-A: the
+ * paper's kernels compute in binary64 internally; Sec. II-A and IV propose a
+ * single precision fast path for GPUs with weak binary64). */
+enum cr_impl {
+  CR_IMPL_AUTO = 0,         /* library default (currently F64_INTERNAL) */
+  CR_IMPL_F64_INTERNAL = 1, /* binary64 fast path + double-double accurate path */
+  CR_IMPL_SPLIT_F32 = 2     /* binary32-only double-float path (not yet built: CR_E_IMPL) */
+};
+
+enum cr_flag {
+  /* every element also takes the accurate path (testing aid); results are
+   * identical by construction, only slower */
+  CR_FLAG_FORCE_FALLBACK = 1u
+};
+
+enum cr_status {
+  CR_OK = 0,
+  CR_E_FUNC = -1,    /* unknown func_id */
+  CR_E_NULL = -2,    /* NULL pointer with n > 0 */
+  CR_E_OVERLAP = -3, /* input and output overlap (other than exact in-place) */
+  CR_E_ALIGN = -4,   /* pointer not aligned to its element size */
+  CR_E_IMPL = -5,    /* unknown or unavailable implementation */
+  CR_E_HIP = -6,     /* a HIP runtime call failed; see cr_last_hip_error() */
+  CR_E_NOMEM = -7,   /* device allocation of library state failed */
+  CR_E_SIZE = -9     /* n too large */
+};
+
+/* out[i] = RN(f(in[i])) for i < n, func = func_id, default implementation.
+ * Paper, Sec. II-A (binary32) and Sec. II-B (binary64). */
+int cr_eval(int func_id, const void *in, void *out, size_t n, void *stream);
+
+/* As cr_eval, with an explicit implementation (enum cr_impl) and flags
+ * (enum cr_flag). */
+int cr_eval_ex(int func_id, int impl, unsigned flags, const void *in, void *out, size_t n,
+               void *stream);
+
+/* 1 if func_id is provided with implementation impl (enum cr_impl) by this
+ * build of the library, else 0. */
+int cr_available(int func_id, int impl);
+
+/* Per-device counters of the current device, cumulative since the last reset
+ * (paper, Sec. III-B: the cost of lanes sent to the accurate path).
+ *   elems          elements submitted through cr_eval / cr_eval_ex
+ *   fallback_lanes elements that failed the fast-path rounding test (or all,
+ *                  with CR_FLAG_FORCE_FALLBACK) and took the accurate path
+ *   fallback_waves wave-level executions of the accurate path (one wave of
+ *                  64 lanes pays once per element slot in which any lane fails)
+ *   escapes        elements whose accurate path could not certify the
+ *                  rounding (expected 0; their output is still the accurate
+ *                  path's result); escape_index[] holds the first ones, as
+ *                  element indices within their call. */
+typedef struct {
+  uint64_t elems;
+  uint64_t fallback_lanes;
+  uint64_t fallback_waves;
+  uint64_t escapes;
+  uint64_t escape_index[16];
+} cr_stats;
+
+/* Zero the current device's counters (stream-ordered). */
+int cr_stats_reset(void *stream);
+/* Copy the current device's counters to *out; synchronises the stream. */
+int cr_stats_read(void *stream, cr_stats *out);
+
+/* Human-readable text for a status code (static storage). */
+const char *cr_status_str(int status);
+/* The last hipError_t seen by this thread inside the library (0 if none). */
+int cr_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,121 @@
+"""Thin ctypes binding of libcr (include/cr.h): argument marshalling only.
+
+Every step of the computation runs in the library's HIP kernels; PyTorch is
+used only for device memory and streams.  Importing this module loads the
+in-tree paper_2605_15547_amd/libcr.so and fails loudly if it is missing.
+"""
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libcr.so")
+
+FUNCS32 = ["expf", "exp2f", "exp10f", "expm1f", "logf", "log2f", "log10f", "log1pf",
+           "rsqrtf", "sinf", "cosf", "sincosf", "tanf", "asinf", "acosf", "atanf",
+           "sinhf", "coshf", "tanhf"]
+FUNC_ID = {name: i for i, name in enumerate(FUNCS32)}
+FUNC_ID["exp"] = 64
+FUNC_ID["log"] = 65
+
+IMPL_AUTO, IMPL_F64_INTERNAL, IMPL_SPLIT_F32 = 0, 1, 2
+FLAG_FORCE_FALLBACK = 1
+
+CR_OK = 0
+STATUS = {0: "CR_OK", -1: "CR_E_FUNC", -2: "CR_E_NULL", -3: "CR_E_OVERLAP", -4: "CR_E_ALIGN",
+          -5: "CR_E_IMPL", -6: "CR_E_HIP", -7: "CR_E_NOMEM", -9: "CR_E_SIZE"}
+
+EXPORTED = ["cr_eval", "cr_eval_ex", "cr_available", "cr_stats_reset", "cr_stats_read",
+            "cr_status_str", "cr_last_hip_error"]
+
+
+class CrError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (what, STATUS.get(status, "?"), status))
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("elems", ctypes.c_uint64), ("fallback_lanes", ctypes.c_uint64),
+                ("fallback_waves", ctypes.c_uint64), ("escapes", ctypes.c_uint64),
+                ("escape_index", ctypes.c_uint64 * 16)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libcr.so not built: run python -c 'import __graft_entry__ as g; "
+                              "g.build()' (expected at %s)" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz = ctypes.c_void_p, ctypes.c_size_t
+        L.cr_eval.argtypes = [ctypes.c_int, vp, vp, sz, vp]
+        L.cr_eval.restype = ctypes.c_int
+        L.cr_eval_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint, vp, vp, sz, vp]
+        L.cr_eval_ex.restype = ctypes.c_int
+        L.cr_available.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.cr_available.restype = ctypes.c_int
+        L.cr_stats_reset.argtypes = [vp]
+        L.cr_stats_read.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.cr_status_str.argtypes = [ctypes.c_int]
+        L.cr_status_str.restype = ctypes.c_char_p
+        L.cr_last_hip_error.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _fid(func):
+    return FUNC_ID[func] if isinstance(func, str) else int(func)
+
+
+def available(func, impl=IMPL_AUTO):
+    return bool(lib().cr_available(_fid(func), impl))
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def eval_ptr(func, in_ptr, out_ptr, n, impl=IMPL_AUTO, flags=0, stream_ptr=None):
+    """Raw call: device pointers (ints), element count, HIP stream pointer."""
+    rc = lib().cr_eval_ex(_fid(func), impl, flags, ctypes.c_void_p(in_ptr),
+                          ctypes.c_void_p(out_ptr), n, stream_ptr)
+    if rc != CR_OK:
+        raise CrError(rc, "cr_eval_ex(%s)" % func)
+
+
+def evaluate(func, x, out=None, impl=IMPL_AUTO, flags=0, stream=None):
+    """Correctly rounded func(x) for a contiguous CUDA tensor x (float32 for the
+    binary32 functions, float64 for exp/log).  sincosf returns shape (2, n)."""
+    import torch
+    fid = _fid(func)
+    want = torch.float64 if fid >= 64 else torch.float32
+    if x.dtype != want or not x.is_cuda or not x.is_contiguous():
+        raise ValueError("expected a contiguous CUDA %s tensor" % want)
+    n = x.numel()
+    nout = 2 * n if fid == FUNC_ID["sincosf"] else n
+    if out is None:
+        out = torch.empty(nout, dtype=want, device=x.device)
+    eval_ptr(fid, x.data_ptr(), out.data_ptr(), n, impl, flags, _stream_ptr(stream))
+    return out.view(2, n) if fid == FUNC_ID["sincosf"] else out.view(x.shape)
+
+
+def stats_reset(stream=None):
+    rc = lib().cr_stats_reset(_stream_ptr(stream))
+    if rc != CR_OK:
+        raise CrError(rc, "cr_stats_reset")
+
+
+def stats_read(stream=None):
+    s = Stats()
+    rc = lib().cr_stats_read(_stream_ptr(stream), ctypes.byref(s))
+    if rc != CR_OK:
+        raise CrError(rc, "cr_stats_read")
+    return {"elems": s.elems, "fallback_lanes": s.fallback_lanes,
+            "fallback_waves": s.fallback_waves, "escapes": s.escapes,
+            "escape_index": list(s.escape_index)[:min(16, s.escapes)]}

@@ -1,0 +1,83 @@
+// cr_dd.h -- error-free transformations and double-double arithmetic (device).
+//
+// The kernels are compiled with -ffp-contract=off so that no a*b+c is fused
+// behind our back; every fused multiply-add below is an explicit fma().
+// Algorithms: Knuth's TwoSum, Dekker's Fast2Sum, the FMA-based TwoProd, and
+// the double-word additions/multiplications analysed by Joldes, Muller and
+// Popescu (ACM TOMS 44(4), 2018): relative errors below 3u^2 (add) and
+// 5u^2 (mul) with u = 2^-53.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cr {
+
+struct dd {
+  double hi, lo;
+};
+
+__device__ __forceinline__ dd two_sum(double a, double b) {
+  double s = a + b;
+  double bb = s - a;
+  double e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+
+// requires |a| >= |b| (or a == 0)
+__device__ __forceinline__ dd fast_two_sum(double a, double b) {
+  double s = a + b;
+  double e = b - (s - a);
+  return {s, e};
+}
+
+__device__ __forceinline__ dd two_prod(double a, double b) {
+  double p = a * b;
+  return {p, fma(a, b, -p)};
+}
+
+// double-word + double
+__device__ __forceinline__ dd dd_add_d(dd x, double y) {
+  dd s = two_sum(x.hi, y);
+  double v = x.lo + s.lo;
+  return fast_two_sum(s.hi, v);
+}
+
+// double-word + double-word (accurate version, relative error <= 3u^2)
+__device__ __forceinline__ dd dd_add(dd x, dd y) {
+  dd s = two_sum(x.hi, y.hi);
+  dd t = two_sum(x.lo, y.lo);
+  double c = s.lo + t.hi;
+  dd v = fast_two_sum(s.hi, c);
+  double w = t.lo + v.lo;
+  return fast_two_sum(v.hi, w);
+}
+
+// double-word * double (relative error <= 2u^2)
+__device__ __forceinline__ dd dd_mul_d(dd x, double y) {
+  dd c = two_prod(x.hi, y);
+  double cl = fma(x.lo, y, c.lo);
+  return fast_two_sum(c.hi, cl);
+}
+
+// double-word * double-word (relative error <= 5u^2)
+__device__ __forceinline__ dd dd_mul(dd x, dd y) {
+  dd c = two_prod(x.hi, y.hi);
+  double tl = x.hi * y.lo;
+  double cl = fma(x.lo, y.hi, tl);
+  cl = c.lo + cl;
+  return fast_two_sum(c.hi, cl);
+}
+
+__device__ __forceinline__ dd dd_neg(dd x) { return {-x.hi, -x.lo}; }
+
+__device__ __forceinline__ dd dd_mul_pow2(dd x, double s) { return {x.hi * s, x.lo * s}; }
+
+// 2^m as a double for -1022 <= m <= 1023
+__device__ __forceinline__ double pow2i(int m) {
+  return __longlong_as_double((long long)(m + 1023) << 52);
+}
+
+__device__ __forceinline__ uint32_t f32_bits(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ float bits_f32(uint32_t b) { return __uint_as_float(b); }
+
+}  // namespace cr

@@ -1,0 +1,206 @@
+// cr_f32_log.h -- correctly rounded logf, log2f, log10f, log1pf (device).
+//
+// Paper, Sec. II-A and Fig. 2 (cr_log2f): the mantissa is brought into
+// [0.75, 1.5), a few leading mantissa bits select table entries, and a
+// polynomial in the reduced argument plus the exponent term reconstruct the
+// result.  Here the table holds a 9-bit reciprocal c_j of each sub-interval
+// (16 entries) and -log_b(c_j) as a double-double, so that
+//     x = 2^e' m,  m in [0.75, 1.5),  t = m c_j - 1  (exact: 24 + 9 bits),
+//     log_b(x) = e' log_b(2) + (-log_b c_j) + K t + t Q(t),
+// with K = 1/ln b on 20 bits (K t exact) and Q a minimax polynomial on
+// t in [-1/32, 1/16].  c_j = 1 on the two sub-intervals next to 1, so for x
+// near 1 the result is K t + t Q(t) with no cancellation.  log1pf uses t = x
+// directly when x is in [-1/32, 1/16) and the same reduction of u = 1 + x
+// otherwise (u is exact for |x| <= 2^29; beyond, the rounding of u moves
+// log(u) by less than 2^-53 and |log(u)| > 20).
+//
+// The binary64 fast path ends with the rounding test of cr_round.h; lanes that
+// fail it run the accurate double-double path below (log1p(t) = 2 atanh(t/(2+t))
+// by its series), as in the exponential family.
+#pragma once
+#include "cr_consts.h"
+#include "cr_round.h"
+
+namespace cr {
+
+enum { LOGK_E = 0, LOGK_2 = 1, LOGK_10 = 2, LOGK_1P = 3 };
+
+struct LogTab {
+  double c[16];
+  double2 L[16];
+};
+
+template <int K>
+__device__ __forceinline__ void log_tab_load(LogTab& t, int tid) {
+  if (tid < 16) {
+    t.c[tid] = LOG_C[tid];
+    t.L[tid] = (K == LOGK_2) ? LOG2_L[tid] : (K == LOGK_10) ? LOG10_L[tid] : LOGE_L[tid];
+  }
+}
+
+// Fast-path error: Q approximation < 2^-60 |t|; the inner sum (|K t + ...| <
+// 0.1) carries one rounding each for t Q and the additions (< 2^-56 absolute);
+// the last addition 1/2 ulp.  |y| >= 0.0128 except on the two sub-intervals
+// around 1 where y = K t + t Q(t) has relative error < 2^-52.  That is below
+// 2 ulps; the test uses 8 (2^3) to absorb the binade of the computed value.
+constexpr int LOG_LOG2E = 3;
+
+template <int K>
+__device__ __forceinline__ double log_C_hi() {
+  return K == LOGK_2 ? 1.0 : K == LOGK_10 ? LOG10_C_HI : LOGE_C_HI;
+}
+template <int K>
+__device__ __forceinline__ double log_C_lo() {
+  return K == LOGK_2 ? 0.0 : K == LOGK_10 ? LOG10_C_LO : LOGE_C_LO;
+}
+template <int K>
+__device__ __forceinline__ double log_K() {
+  return K == LOGK_2 ? LOG2_K : K == LOGK_10 ? LOG10_K : 1.0;
+}
+template <int K>
+__device__ __forceinline__ double log_Q(double t) {
+  if (K == LOGK_2) {
+    double p = LOG2_Q[LOG2_Q_DEG];
+#pragma unroll
+    for (int i = LOG2_Q_DEG - 1; i >= 0; i--) p = fma(p, t, LOG2_Q[i]);
+    return p;
+  } else if (K == LOGK_10) {
+    double p = LOG10_Q[LOG10_Q_DEG];
+#pragma unroll
+    for (int i = LOG10_Q_DEG - 1; i >= 0; i--) p = fma(p, t, LOG10_Q[i]);
+    return p;
+  } else {
+    double p = LOGE_Q[LOGE_Q_DEG];
+#pragma unroll
+    for (int i = LOGE_Q_DEG - 1; i >= 0; i--) p = fma(p, t, LOGE_Q[i]);
+    return p;
+  }
+}
+
+// log1p(t) for a double-double t with |t| <= 1/16: 2 atanh(s), s = t/(2+t),
+// series in s^2 (terms of index >= 6 in binary64, the rest in double-double).
+__device__ __forceinline__ dd log1p_dd(dd t) {
+  dd den = dd_add_d(t, 2.0);
+  double q1 = t.hi / den.hi;
+  dd pr = dd_mul_d(den, q1);
+  dd r = dd_add(t, dd_neg(pr));
+  double q2 = r.hi / den.hi;
+  dd s = fast_two_sum(q1, q2);
+  dd s2 = dd_mul(s, s);
+  double ph = INV_ODD[ATANH_N].x;
+#pragma unroll
+  for (int k = ATANH_N - 1; k >= 6; k--) ph = fma(ph, s2.hi, INV_ODD[k].x);
+  dd p = {ph, 0.0};
+#pragma unroll
+  for (int k = 5; k >= 0; k--) {
+    double2 c = INV_ODD[k];
+    p = dd_add(dd_mul(p, s2), dd{c.x, c.y});
+  }
+  dd y = dd_mul(p, s);
+  return {2.0 * y.hi, 2.0 * y.lo};
+}
+
+// Shared set-up: u (= x, or 1 + x for log1pf), the decomposition u = 2^e' m
+// with m in [0.75, 1.5), the table entries and the reduced argument t.
+struct LogSetup {
+  double u, m, c, t;
+  double2 L;
+  int e2, near;
+};
+
+template <int K>
+__device__ __forceinline__ LogSetup log_setup(float xf, const LogTab& tb) {
+  LogSetup S;
+  double x = (double)xf;
+  S.u = (K == LOGK_1P) ? 1.0 + x : x;
+  // u = 2^e m, m in [1,2); index j = top 4 fraction bits; fold m >= 1.5 to m/2
+  int hi = __double2hiint(S.u);
+  int j = (hi >> 16) & 15;
+  int fold = j >> 3;
+  S.e2 = ((hi >> 20) & 0x7ff) - 1023 + fold;
+  S.m = __hiloint2double((hi & 0x000fffff) | ((1023 - fold) << 20), __double2loint(S.u));
+  S.c = tb.c[j];
+  S.L = tb.L[j];
+  S.t = fma(S.m, S.c, -1.0);
+  S.near = 0;
+  if (K == LOGK_1P) {
+    S.near = (x >= -0.03125) & (x < 0.0625);
+    if (S.near) {
+      S.t = x;
+      S.e2 = 0;
+      S.L = make_double2(0.0, 0.0);
+    }
+  }
+  return S;
+}
+
+// NaN (quieted), u <= 0 (-inf at 0, NaN below), u = +inf, log1p(+-0) = +-0.
+template <int K>
+__device__ __forceinline__ bool log_special(float xf, double u, float& res) {
+  if (xf != xf) {
+    res = bits_f32(f32_bits(xf) | 0x00400000u);
+    return true;
+  }
+  if (K == LOGK_1P && xf == 0.0f) {
+    res = xf;
+    return true;
+  }
+  if (!(u > 0.0)) {
+    res = u == 0.0 ? -INFINITY : bits_f32(0x7fc00000u);
+    return true;
+  }
+  if (u == INFINITY) {
+    res = INFINITY;
+    return true;
+  }
+  return false;
+}
+
+template <int K>
+__device__ __forceinline__ float log_fast(float xf, const LogTab& tb, bool& ok) {
+  LogSetup S = log_setup<K>(xf, tb);
+  double t = S.t;
+  double Q = log_Q<K>(t);
+  double ed = (double)S.e2;
+  dd A = fast_two_sum(ed * log_C_hi<K>(), S.L.x);  // |e' C| >= |L| unless e' = 0
+  double inner = fma(t, Q, A.lo + fma(ed, log_C_lo<K>(), S.L.y));
+  double yh = A.hi + fma(log_K<K>(), t, inner);
+  float res = round_f32_fast<LOG_LOG2E>(yh, ok);
+  if (log_special<K>(xf, S.u, res)) ok = true;
+  return res;
+}
+
+// Accurate path: t rebuilt exactly as a double-double (plus, for log1pf, the
+// rounding error of u = 1 + x scaled like m), then
+// y = e' log_b 2 + (-log_b c_j) + log1p(t) / ln b in double-double.
+template <int K>
+__device__ __noinline__ AccResult log_accurate(float xf, const LogTab& tb) {
+  LogSetup S = log_setup<K>(xf, tb);
+  float sp;
+  if (log_special<K>(xf, S.u, sp)) return {sp, 1};
+  dd t;
+  if (S.near) {
+    t = {S.t, 0.0};
+  } else {
+    dd p = two_prod(S.m, S.c);
+    t = fast_two_sum(p.hi - 1.0, p.lo);  // p.hi - 1 is exact (p.hi in [0.96, 1.07])
+    if (K == LOGK_1P) {
+      // (1 + x) - u exactly (Fast2Sum: |x| >= 1 whenever u is inexact), scaled like m
+      double x = (double)xf;
+      double ulo = (1.0 - (S.u - x)) * pow2i(-S.e2);
+      t = dd_add_d(t, ulo * S.c);
+    }
+  }
+  dd l = log1p_dd(t);
+  if (K == LOGK_2) l = dd_mul(l, dd{INV_LN2_HI, INV_LN2_LO});
+  if (K == LOGK_10) l = dd_mul(l, dd{INV_LN10_HI, INV_LN10_LO});
+  dd C = K == LOGK_2 ? dd{1.0, 0.0}
+                     : K == LOGK_10 ? dd{LOG10_2_HI, LOG10_2_LO} : dd{LN2_HI, LN2_LO};
+  dd y = dd_add(dd_mul_d(C, (double)S.e2), dd{S.L.x, S.L.y});
+  y = dd_add(y, l);
+  bool ok;
+  float r = round_f32_dd(y.hi, y.lo, 0x1p-85, ok);
+  return {r, ok ? 1 : 0};
+}
+
+}  // namespace cr

@@ -1,0 +1,90 @@
+// cr_round.h -- final correct rounding of binary32 results (device).
+//
+// The paper's CPU kernels compute in binary64 and finish with round-to-zero
+// plus a sticky bit before the conversion to binary32 (Sec. II-A, Fig. 1), and
+// their FP64 functions pair an accurate main path with a correct-rounding test
+// and a slower path for the lanes that fail it (Sec. II-B).  On the GPU there
+// is no static rounding, so both ideas are expressed with round-to-nearest:
+//
+//  * fast path: the approximation yh (binary64) is within E ulps of f(x).
+//    RN_f32 is monotone, so if RN_f32(yh - E ulp) == RN_f32(yh + E ulp) every
+//    real in between -- f(x) included -- rounds to that same float.
+//  * accurate path: a double-double (h, l) within a relative bound drel of
+//    f(x).  Both ends of the enclosure are formed as round-to-odd binary64
+//    numbers (truncate, then force the last bit to 1 if inexact); converting a
+//    round-to-odd value with >= 2 extra bits to binary32 gives the correctly
+//    rounded binary32 value of the exact number (Boldo and Melquiond,
+//    "Emulation of FMA and correctly rounded sums: proved algorithms using
+//    rounding to odd", IEEE TC 57(4), 2008).  Equal ends => correct result.
+#pragma once
+#include "cr_dd.h"
+
+namespace cr {
+
+// result of an out-of-line accurate path: the rounded value and whether its
+// rounding was certified (returned in registers)
+struct AccResult {
+  float r;
+  int ok;
+};
+
+// ulp of |y| in binary64 (y normal, nonzero): 2^(exponent(y) - 52)
+__device__ __forceinline__ double ulp53(double y) {
+  uint32_t hi = (uint32_t)__double2hiint(y) & 0x7ff00000u;
+  return __hiloint2double((int)hi, 0) * 0x1p-52;
+}
+
+// 2^(exponent(y) + k) for normal y and a small k (exponent field arithmetic;
+// the result must stay normal, which holds for every use here)
+__device__ __forceinline__ double pow2_of_exp(double y, int k) {
+  int hi = (__double2hiint(y) & 0x7ff00000) + (k << 20);
+  return __hiloint2double(hi, 0);
+}
+
+// y * 2^m by adding m to the exponent field (y normal, result normal)
+__device__ __forceinline__ double scale_exp(double y, int m) {
+  return __hiloint2double(__double2hiint(y) + (m << 20), __double2loint(y));
+}
+
+// Fast-path rounding: *ok is set when every real within 2^LOG2E ulps of yh
+// rounds to the returned float.
+template <int LOG2E>
+__device__ __forceinline__ float round_f32_fast(double yh, bool& ok) {
+  double d = pow2_of_exp(yh, LOG2E - 52);
+  float a = (float)(yh - d);
+  float b = (float)(yh + d);
+  ok = a == b;
+  return b;
+}
+
+// Same, with an absolute error bound instead of a count of ulps.
+__device__ __forceinline__ float round_f32_fast_abs(double yh, double err, bool& ok) {
+  float a = (float)(yh - err);
+  float b = (float)(yh + err);
+  ok = a == b;
+  return b;
+}
+
+// Round-to-odd of h + l into binary64, given h = RN(h + l).
+__device__ __forceinline__ double ro53(double h, double l) {
+  long long b = __double_as_longlong(h);
+  if (l != 0.0) {
+    if ((l < 0.0) != (h < 0.0)) b -= 1;
+    b |= 1;
+  }
+  return __longlong_as_double(b);
+}
+
+// Accurate-path rounding of h + l (|l| <= ulp(h)/2) known to within a relative
+// error drel (drel already includes a safety margin).
+__device__ __forceinline__ float round_f32_dd(double h, double l, double drel, bool& ok) {
+  double e = fabs(h) * drel;
+  dd lo = fast_two_sum(h, l - e);
+  dd hi = fast_two_sum(h, l + e);
+  float a = (float)ro53(lo.hi, lo.lo);
+  float b = (float)ro53(hi.hi, hi.lo);
+  ok = a == b;
+  return b;
+}
+
+}  // namespace cr

@@ -1,0 +1,279 @@
+"""Generates paper_2605_15547_amd/csrc/cr_consts.h: tables and polynomial
+coefficients of the GPU kernels.
+
+Everything is computed here with mpmath at high precision and rounded to
+binary64 (or to double-double pairs hi + lo).  Polynomial coefficients come
+from a weighted minimax fit (Lawson's iteratively reweighted least squares);
+each approximation's error bound is measured on a dense grid with the ROUNDED
+coefficients and inflated by 25%, and is written next to the coefficients so
+the kernels' rounding tests can budget for it.
+
+The paper prints no coefficients (its listings elide them); these are this
+project's own.  Run:  python paper_2605_15547_amd/gen/gen_consts.py
+"""
+import os
+import sys
+
+import mpmath as mp
+
+mp.mp.prec = 200
+HERE = os.path.dirname(os.path.abspath(__file__))
+OUT = os.path.join(os.path.dirname(HERE), "csrc", "cr_consts.h")
+
+
+# ------------------------------------------------------------ rounding utils
+def d(x):
+    """round to binary64 (RN)"""
+    return float(mp.mpf(x))
+
+
+def dd(x):
+    """double-double (hi, lo) with hi = RN(x), lo = RN(x - hi)"""
+    x = mp.mpf(x)
+    hi = float(x)
+    lo = float(x - mp.mpf(hi))
+    return hi, lo
+
+
+def td(x):
+    hi = float(x)
+    r = x - mp.mpf(hi)
+    mid = float(r)
+    lo = float(r - mp.mpf(mid))
+    return hi, mid, lo
+
+
+def split_bits(x, bits):
+    """x rounded to `bits` significant bits, as a double"""
+    x = mp.mpf(x)
+    e = int(mp.floor(mp.log(abs(x), 2)))
+    q = mp.mpf(2) ** (e - bits + 1)
+    return float(mp.nint(x / q) * q)
+
+
+def hexd(v):
+    return float(v).hex()
+
+
+# --------------------------------------------------------- minimax fitting
+def cheb_nodes(a, b, n):
+    a, b = mp.mpf(a), mp.mpf(b)
+    return [(a + b) / 2 + (b - a) / 2 * mp.cos(mp.pi * (2 * i + 1) / (2 * n)) for i in range(n)]
+
+
+def lawson_fit(g, w, a, b, powers, npts=500, iters=40):
+    """Coefficients c_k (mp) minimising max |w(x) (g(x) - sum c_k x^p_k)| on [a,b]."""
+    xs = cheb_nodes(a, b, npts) + [mp.mpf(a), mp.mpf(b)]
+    gs = [g(x) for x in xs]
+    ws = [w(x) for x in xs]
+    W = [mp.mpf(1)] * len(xs)
+    m = len(powers)
+    c = None
+    for _ in range(iters):
+        A = mp.matrix(m, m)
+        B = mp.matrix(m, 1)
+        for x, gx, wx, Wi in zip(xs, gs, ws, W):
+            s = Wi * wx * wx
+            pw = [x ** p for p in powers]
+            for k in range(m):
+                B[k] += s * gx * pw[k]
+                for l in range(m):
+                    A[k, l] += s * pw[k] * pw[l]
+        c = mp.lu_solve(A, B)
+        errs = [abs(wx * (gx - sum(c[k] * x ** powers[k] for k in range(m))))
+                for x, gx, wx in zip(xs, gs, ws)]
+        tot = sum(Wi * e for Wi, e in zip(W, errs))
+        W = [Wi * e / tot for Wi, e in zip(W, errs)]
+    return [c[k] for k in range(m)]
+
+
+def max_err(fn, a, b, n=4000):
+    """max |fn(x)| on a dense grid of [a,b] (plus Chebyshev points)"""
+    a, b = mp.mpf(a), mp.mpf(b)
+    pts = [a + (b - a) * i / n for i in range(n + 1)] + cheb_nodes(a, b, 1000)
+    return max(abs(fn(x)) for x in pts)
+
+
+def log2_of(x):
+    return float(mp.log(x, 2)) if x > 0 else -9999.0
+
+
+# ------------------------------------------------------------- header text
+lines = []
+
+
+def emit(s=""):
+    lines.append(s)
+
+
+def emit_dd_table(name, vals, comment):
+    emit("// " + comment)
+    emit("__device__ __constant__ const double2 %s[%d] = {" % (name, len(vals)))
+    for v in vals:
+        hi, lo = dd(v)
+        emit("  {%s, %s}," % (hexd(hi), hexd(lo)))
+    emit("};")
+
+
+def emit_arr(name, vals, comment, ctype="double"):
+    """Coefficient arrays are left non-const on purpose: the compiler then
+    loads them once per kernel into scalar registers (uniform loads) and feeds
+    them to v_fma_f64 as its scalar operand, instead of rebuilding each 64-bit
+    constant in vector registers at every use."""
+    emit("// " + comment)
+    emit("__device__ __constant__ %s %s[%d] = {%s};" %
+         (ctype, name, len(vals), ", ".join(hexd(v) for v in vals)))
+
+
+def emit_const(name, v, comment=""):
+    emit("#define %s (%s)%s" % (name, hexd(v), ("  /* " + comment + " */") if comment else ""))
+
+
+# =================================================================== exp family
+def gen_exp():
+    ln2 = mp.log(2)
+    emit("// ---- exponential family (expf, exp2f, exp10f, expm1f, sinhf, coshf, tanhf) ----")
+    emit_dd_table("EXP_T16", [mp.power(2, mp.mpf(j) / 16) for j in range(16)],
+                  "2^(j/16), j = 0..15, as double-double (hi, lo)")
+    # Cody-Waite split of ln2/16: C1 has 41 significant bits so that k*C1 is
+    # exact for |k| < 2^12 and x - k*C1 is exact (see kernel comment).
+    c = ln2 / 16
+    c1 = split_bits(c, 41)
+    r1 = c - mp.mpf(c1)
+    c2 = float(r1)
+    c3 = float(r1 - mp.mpf(c2))
+    emit_const("LN2_16_C1", c1, "ln2/16 rounded to 41 bits")
+    emit_const("LN2_16_C2", c2, "next 53 bits of ln2/16")
+    emit_const("LN2_16_C3", c3, "next 53 bits of ln2/16")
+    emit_const("INV_LN2_16", d(16 / ln2), "16/ln2")
+    h, l = dd(ln2 / 16)
+    emit_const("LN2_16_HI", h, "ln2/16 hi")
+    emit_const("LN2_16_LO", l, "ln2/16 lo")
+    h, l = dd(16 * mp.log(10) / ln2)
+    emit_const("LOG2_10_16_HI", h, "16 log2(10) hi")
+    emit_const("LOG2_10_16_LO", l, "16 log2(10) lo")
+    h, l = dd(mp.log(10))
+    emit_const("LN10_HI", h, "ln 10 hi")
+    emit_const("LN10_LO", l, "ln 10 lo")
+    h, l = dd(ln2)
+    emit_const("LN2_HI", h, "ln 2 hi")
+    emit_const("LN2_LO", l, "ln 2 lo")
+
+    # fast path: e^r - 1 = r + r^2 P(r), |r| <= RHO
+    rho = mp.mpf("0.02167")  # (1/2 + 2^-40) ln2/16 < 0.02167
+    for deg in range(3, 9):
+        powers = list(range(deg + 1))
+        cs = lawson_fit(lambda r: (mp.expm1(r) - r) / (r * r) if r != 0 else mp.mpf(0.5),
+                        lambda r: r * r, -rho, rho, powers)
+        cd = [d(v) for v in cs]
+        err = max_err(lambda r: mp.expm1(r) - r - r * r * sum(mp.mpf(cd[k]) * r ** k
+                                                              for k in range(len(cd))),
+                      -rho, rho)
+        if err < mp.mpf(2) ** -63:
+            break
+    bound = err * mp.mpf("1.25")
+    emit("// e^r - 1 = r + r^2 (P0 + P1 r + ...), |r| <= %s; |error| <= 2^%.2f (absolute)"
+         % (mp.nstr(rho, 6), log2_of(bound)))
+    emit_arr("EXPM1_P", cd, "minimax coefficients P0.. (degree %d)" % (len(cd) - 1))
+    emit("#define EXPM1_P_DEG %d" % (len(cd) - 1))
+    emit_const("EXPM1_P_ERR", d(bound), "bound on the approximation error")
+
+    # accurate path: Taylor series of e^r - 1 to degree N in double-double
+    N = 14
+    rem = rho ** (N + 1) / mp.factorial(N + 1) * 2
+    emit("// 1/k!, k = 0..%d, double-double (Taylor series of e^r, |r| <= %s: "
+         "remainder <= 2^%.1f)" % (N, mp.nstr(rho, 6), log2_of(rem)))
+    emit("#define EXP_TAYLOR_N %d" % N)
+    emit_dd_table("INV_FACT", [1 / mp.factorial(k) for k in range(N + 1)], "1/k!")
+    emit()
+
+
+# =================================================================== log family
+def log_intervals():
+    """The 16 intervals of the reduced mantissa and their reciprocals c_j.
+
+    m in [1,2) is indexed by its top 4 fraction bits j; for j >= 8 the kernel
+    uses m' = m/2 in [0.75, 1) (and e' = e + 1), so the value range is
+    [0.75, 1.5).  c_j ~ 1/center rounded to 9 significant bits (so m * c_j is
+    exact for 24-bit m), and c_j = 1 on the two intervals next to 1 so that
+    log(x) near x = 1 is t + ... with no cancellation."""
+    out = []
+    for j in range(16):
+        if j < 8:
+            lo, hi = 1 + mp.mpf(j) / 16, 1 + mp.mpf(j + 1) / 16
+        else:
+            lo, hi = (1 + mp.mpf(j) / 16) / 2, (1 + mp.mpf(j + 1) / 16) / 2
+        if j in (0, 15):
+            c = mp.mpf(1)
+        else:
+            c = mp.mpf(split_bits(2 / (lo + hi), 9))
+        out.append((lo, hi, c))
+    return out
+
+
+def gen_log():
+    emit("// ---- logarithm family (logf, log2f, log10f, log1pf) ----")
+    iv = log_intervals()
+    tmin = min(lo * c - 1 for lo, hi, c in iv)
+    tmax = max(hi * c - 1 for lo, hi, c in iv)
+    emit("// reduced argument t = m c_j - 1 lies in [%s, %s]" % (mp.nstr(tmin, 8), mp.nstr(tmax, 8)))
+    emit_arr("LOG_C", [float(c) for _, _, c in iv], "c_j (9 significant bits)")
+    # K = 1/ln b on 20 bits: K t is exact for the <= 33-bit t of binary32
+    # inputs, and Q(0) = 1/ln b - K is tiny, so rounding Q's coefficients costs
+    # nothing measurable
+    bases = [("E", mp.mpf(1), mp.mpf(1)),
+             ("2", 1 / mp.log(2), mp.mpf(split_bits(1 / mp.log(2), 20))),
+             ("10", 1 / mp.log(10), mp.mpf(split_bits(1 / mp.log(10), 20)))]
+    for name, inv_ln, K in bases:
+        emit_dd_table("LOG%s_L" % name, [-mp.log(c) * inv_ln for _, _, c in iv],
+                      "-log_b(c_j), b = %s, double-double" % ("e" if name == "E" else name))
+    # e' * C with C_hi on 44 bits so that e' C_hi is exact for |e'| < 2^9
+    for name, v in (("E", mp.log(2)), ("10", mp.log10(2))):
+        hi = split_bits(v, 44)
+        emit_const("LOG%s_C_HI" % name, hi, "log_b(2), 44 bits")
+        emit_const("LOG%s_C_LO" % name, d(v - mp.mpf(hi)), "log_b(2) - C_HI")
+    a, b = tmin * mp.mpf("1.0001"), tmax * mp.mpf("1.0001")
+    for name, inv_ln, K in bases:
+        g = (lambda il, KK: (lambda t: (mp.log1p(t) * il / t - KK) if t != 0 else il - KK))(inv_ln, K)
+        for deg in range(9, 16):
+            cs = lawson_fit(g, lambda t: mp.mpf(1), a, b, list(range(deg + 1)), npts=160, iters=16)
+            cd = [d(v) for v in cs]
+            err = max_err(lambda t: g(t) - sum(mp.mpf(cd[k]) * t ** k for k in range(len(cd))), a, b)
+            if err < mp.mpf(2) ** -62:
+                break
+        bound = err * mp.mpf("1.25")
+        emit("// log_b(1+t) = K t + t Q(t), K = %s, t in [%s, %s]; |Q error| <= 2^%.2f"
+             % (mp.nstr(K, 5), mp.nstr(a, 6), mp.nstr(b, 6), log2_of(bound)))
+        emit_arr("LOG%s_Q" % name, cd, "Q coefficients (degree %d)" % (len(cd) - 1))
+        emit("#define LOG%s_Q_DEG %d" % (name, len(cd) - 1))
+        emit_const("LOG%s_K" % name, d(K))
+    # accurate path
+    for name, inv_ln, K in bases[1:]:
+        h, l = dd(inv_ln)
+        emit_const("INV_LN%s_HI" % name, h)
+        emit_const("INV_LN%s_LO" % name, l)
+    h, l = dd(mp.log10(2))
+    emit_const("LOG10_2_HI", h)
+    emit_const("LOG10_2_LO", l)
+    # 2 atanh(s) = 2 sum s^(2k+1)/(2k+1), |s| <= 0.0304: 12 terms leave < 2^-120
+    N = 12
+    emit("#define ATANH_N %d" % N)
+    emit_dd_table("INV_ODD", [mp.mpf(1) / (2 * k + 1) for k in range(N + 1)], "1/(2k+1)")
+    emit()
+
+
+def main():
+    emit("// Generated by paper_2605_15547_amd/gen/gen_consts.py -- do not edit.")
+    emit("// Tables and polynomial coefficients of the correctly rounded kernels.")
+    emit("#pragma once")
+    emit("#include <hip/hip_runtime.h>")
+    emit()
+    gen_exp()
+    gen_log()
+    with open(OUT, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", OUT)
+
+
+if __name__ == "__main__":
+    main()
