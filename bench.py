@@ -34,6 +34,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2605_15547_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(func, n):
+    """HBM bytes per launch of func's kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE runs (calibrated against a plain copy), or None when
+    the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_source_hash() or t.get("elems_per_launch") != n:
+        return None
+    return t["hbm_bytes_per_launch"].get(func)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -42,6 +66,9 @@ def main():
     ap.add_argument("--n", type=int, default=26, help="log2 of elements per function")
     ap.add_argument("--impl", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="also time a plain copy of one input (profiler calibration)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: the method is an elementwise map with no "
@@ -104,33 +131,51 @@ def main():
     total_elems = n * len(funcs) * a.steps
     value = total_elems / wall / 1e9
     dom = max(funcs, key=lambda f: per[f]["ms"])
-    roof = {"bound": "hbm", "kernel": "k_map_f32_vec<%s>" % dom,
+    roof = {"bound": "hbm", "kernel": "k_map_f32<%s>" % dom,
             "achieved": per[dom]["gb_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(per[dom]["gb_s"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(per[dom]["gb_s"] / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom, n),
             "bytes_per_elem": 8, "elems_per_launch": n}
+
+    copy_ms = None
+    if a.copy_ref:
+        # a plain device-to-device copy of the same size: the reference used to
+        # calibrate the HBM byte counters of the profiler (FETCH_SIZE/WRITE_SIZE)
+        src, dst = xs[funcs[0]], outs[funcs[0]]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(a.steps):
+            dst.copy_(src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        copy_ms = e0.elapsed_time(e1) / a.steps
 
     cpu = None
     if not a.no_cpu_baseline:
+        # the oracle as it is, on a bounded sample: consecutive 2^14-element
+        # slices of each function's workload, round robin, for about 12 s
         from oracle import oracle as O
         O.build()
         threads = O.default_threads()
-        m = 1 << 13
+        m, cnt, rounds = 1 << 14, 0, 0
         t0 = time.perf_counter()
-        cnt = 0
-        for f in funcs:
-            O.evaluate(f, host[f][:m], threads)
-            cnt += m
+        while time.perf_counter() - t0 < a.cpu_seconds:
+            for f in funcs:
+                O.evaluate(f, host[f][rounds * m:(rounds + 1) * m], threads)
+                cnt += m
+            rounds += 1
         dt = time.perf_counter() - t0
         cpu = {"value": round(cnt / dt / 1e9, 6), "unit": "Gelem/s", "cores": threads,
                "kind": "oracle",
-               "sample": "first %d inputs of each function's workload (%d elements), "
-                         "Ziv loop over fixed-point ball arithmetic, %.1f s" % (m, cnt, dt)}
+               "sample": "first %d inputs of each of the %d functions' workloads (%d elements, "
+                         "%.1f s); Ziv loop over fixed-point ball arithmetic"
+                         % (rounds * m, len(funcs), cnt, dt)}
 
     rec = {"metric": "correctly rounded Gelem/s (exp/log family, binary32), bit-exact",
            "value": round(value, 2), "unit": "Gelem/s", "n_gpus": 1, "steps": a.steps,
            "warmup": a.warmup, "ms_per_step": round(wall / a.steps * 1e3, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64 (binary32 in/out)", "data": "synthetic",
+           "dtype": "f64", "data": "synthetic",
            "config": {"workload": "exp/log family, 2^%d binary32 inputs per function" % a.n,
                       "functions": funcs, "missing": missing, "elems_per_function": n,
                       "impl": "f64_internal" if a.impl in (0, 1) else "split_f32"},
@@ -139,6 +184,9 @@ def main():
                         "escapes": st["escapes"],
                         "lane_rate": st["fallback_lanes"] / max(1, total_elems)},
            "roofline": roof, "cpu_baseline": cpu}
+    if copy_ms is not None:
+        rec["copy_ref"] = {"ms": round(copy_ms, 4), "bytes": 8 * n,
+                           "gb_s": round(8 * n / (copy_ms * 1e-3) / 1e9, 1)}
     print(json.dumps(rec), flush=True)
 
 

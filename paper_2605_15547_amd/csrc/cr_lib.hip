@@ -16,6 +16,7 @@
 #include "../../include/cr.h"
 #include "cr_f32_exp.h"
 #include "cr_f32_log.h"
+#include "cr_f32_rsqrt.h"
 
 using namespace cr;
 
@@ -76,6 +77,19 @@ struct OpLog {
   }
   static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
     return log_accurate<K>(x, t);
+  }
+};
+
+// rsqrtf decides its rounding exactly in the fast path: nothing is deferred.
+struct OpRsqrt {
+  using Tab = NoTab;
+  static __device__ __forceinline__ void load(Tab&, int) {}
+  static __device__ __forceinline__ float fast(float x, const Tab&, bool& ok) {
+    return rsqrt_fast(x, ok);
+  }
+  static __device__ __noinline__ AccResult accurate(float x, const Tab&) {
+    bool ok;
+    return {rsqrt_fast(x, ok), 1};
   }
 };
 
@@ -356,7 +370,7 @@ int launch_map_f32(const float* in, float* out, size_t n, hipStream_t s, unsigne
 }
 
 bool func_valid(int f) { return (f >= 0 && f < CR_NUM_F32) || f == CR_EXP || f == CR_LOG; }
-bool func_built(int f) { return f >= CR_EXPF && f <= CR_LOG1PF; }
+bool func_built(int f) { return f >= CR_EXPF && f <= CR_RSQRTF; }
 
 int dispatch_f32(int f, const float* in, float* out, size_t n, hipStream_t s, unsigned flags,
                  DevStats* st) {
@@ -369,6 +383,7 @@ int dispatch_f32(int f, const float* in, float* out, size_t n, hipStream_t s, un
     case CR_LOG2F: return launch_map_f32<OpLog<LOGK_2>>(in, out, n, s, flags, st);
     case CR_LOG10F: return launch_map_f32<OpLog<LOGK_10>>(in, out, n, s, flags, st);
     case CR_LOG1PF: return launch_map_f32<OpLog<LOGK_1P>>(in, out, n, s, flags, st);
+    case CR_RSQRTF: return launch_map_f32<OpRsqrt>(in, out, n, s, flags, st);
   }
   return CR_E_FUNC;
 }

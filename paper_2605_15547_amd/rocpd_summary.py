@@ -1,0 +1,54 @@
+"""Summarise rocprofv3 SQLite output (kernel-trace stats, or one PMC counter per
+dispatch) into a short text table.  Usage:
+  python -m paper_2605_15547_amd.rocpd_summary stats   <results.db>
+  python -m paper_2605_15547_amd.rocpd_summary counter <results.db>
+"""
+import re
+import sqlite3
+import sys
+from collections import defaultdict
+
+
+FUNCS = {"OpExp<0>": "expf", "OpExp<1>": "exp2f", "OpExp<2>": "exp10f", "OpExp<3>": "expm1f",
+         "OpLog<0>": "logf", "OpLog<1>": "log2f", "OpLog<2>": "log10f", "OpLog<3>": "log1pf",
+         "OpRsqrt": "rsqrtf"}
+
+
+def short(name):
+    """k_map_f32<OpLog<3>> (log1pf) style names for the library's kernels."""
+    name = name.replace("(anonymous namespace)::", "")
+    m = re.match(r"void (k_\w+)<(\w+(?:<\d+>)?) ?>", name)
+    if m:
+        op = m.group(2)
+        return "%s<%s> (%s)" % (m.group(1), op, FUNCS.get(op, "?"))
+    return name.split("(")[0][:60]
+
+
+def stats(db):
+    rows = db.execute("select name, duration from kernels").fetchall()
+    agg = defaultdict(list)
+    for n, d in rows:
+        agg[short(n)].append(d)
+    print("%-44s %6s %12s %10s %10s %10s" % ("kernel", "calls", "total_ns", "avg_ns", "min_ns",
+                                             "max_ns"))
+    for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        print("%-44s %6d %12d %10.0f %10d %10d" % (k, len(v), sum(v), sum(v) / len(v), min(v),
+                                                    max(v)))
+
+
+def counter(db):
+    cols = [r[1] for r in db.execute("pragma table_info(counters_collection)")]
+    q = "select * from counters_collection"
+    agg = defaultdict(list)
+    for r in db.execute(q):
+        d = dict(zip(cols, r))
+        agg[(short(d.get("kernel_name", "?")), d.get("counter_name"))].append(d.get("value"))
+    print("%-44s %-12s %6s %14s" % ("kernel", "counter", "calls", "avg_per_dispatch"))
+    for (k, c), v in sorted(agg.items()):
+        print("%-44s %-12s %6d %14.1f" % (k, c, len(v), sum(v) / len(v)))
+
+
+if __name__ == "__main__":
+    mode, path = sys.argv[1], sys.argv[2]
+    db = sqlite3.connect(path)
+    stats(db) if mode == "stats" else counter(db)
