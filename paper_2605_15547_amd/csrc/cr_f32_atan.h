@@ -1,0 +1,186 @@
+// cr_f32_atan.h -- correctly rounded atanf, asinf, acosf (device).
+//
+// atanf, asinf and acosf are among the paper's functions (Sec. II-A); the
+// paper's table sizes for cr_atanf (Table I: 0.125 KB, 16 binary64 values)
+// suggest a 16-entry atan(c_j) table, used here as follows.  All three are
+// atan(Y/X) for Y, X >= 0:
+//   atan x = atan(|x| / 1),   asin x = atan(|x| / s),   acos x = atan(s / x)
+//   (x >= 0) or pi - atan(s / |x|) (x < 0), with s = sqrt(1 - x^2).
+// With z = min(Y, X) / max(Y, X) and c = j/16, j = min(rint(16 z), 15):
+//   Y <= X:  atan(Y/X) = atan(c) + atan(t),           t = (Y - c X)/(X + c Y)
+//   Y >  X:  atan(Y/X) = (pi/2 - atan(c)) - atan(t),  t = (X - c Y)/(Y + c X)
+// |t| <= 1/31, and atan t = t + t^3 P(t^2).  c X and c Y are exact products
+// inside the FMAs, so t carries one rounding of each of numerator,
+// denominator and quotient.  j = 0 gives c = 0 and t = Y/X exactly rounded,
+// so small results (atan/asin of small x, acos near 1) keep full relative
+// accuracy.  An error in s moves asin and acos by at most x ds and s ds
+// respectively, below 2^-52.4 of the result, so s needs no extra precision
+// in the fast path.
+#pragma once
+#include "cr_consts.h"
+#include "cr_round.h"
+
+namespace cr {
+
+enum { ATANK_ATAN = 0, ATANK_ASIN = 1, ATANK_ACOS = 2 };
+
+struct AtanTab {
+  double4 t[16];
+};
+
+__device__ __forceinline__ void atan_tab_load(AtanTab& t, int tid) {
+  if (tid < 16) t.t[tid] = ATAN_T[tid];
+}
+
+// atan(Y/X) = hi + lo (not normalised), Y, X >= 0, not both zero
+__device__ __forceinline__ void atan_ratio_fast(double Y0, double X0, const AtanTab& tb,
+                                                double& hi, double& lo) {
+  bool inv = Y0 > X0;
+  double Y = inv ? X0 : Y0, X = inv ? Y0 : X0;
+  float zf = (float)Y * __builtin_amdgcn_rcpf((float)X);  // index only: an estimate suffices
+  int j = (int)rintf(16.0f * zf);
+  j = j > 15 ? 15 : (j < 0 ? 0 : j);
+  double c = (double)j * 0.0625;
+  double t = fma(-c, X, Y) / fma(c, Y, X);
+  double t2 = t * t;
+  double p = ATAN_P[ATAN_P_DEG];
+#pragma unroll
+  for (int i = ATAN_P_DEG - 1; i >= 0; i--) p = fma(p, t2, ATAN_P[i]);
+  double at = fma(t * t2, p, t);
+  double4 T = tb.t[j];
+  hi = inv ? T.z : T.x;
+  lo = (inv ? T.w : T.y) + (inv ? -at : at);
+}
+
+// Fast-path error: t has relative error <= 3 2^-53 (+ P < 2^-66), so atan t
+// is within 2^-56.7 absolute (|t| <= 1/31); the result is >= |t|/2 for j = 0
+// and >= 0.03 otherwise; with the final addition this is below 4 ulps.  The
+// test uses 16.
+constexpr int ATAN_LOG2E = 4;
+
+__device__ __forceinline__ bool atan_special(float xf, int kind, float& res) {
+  if (xf != xf) {
+    res = bits_f32(f32_bits(xf) | 0x00400000u);
+    return true;
+  }
+  if (kind != ATANK_ATAN && fabsf(xf) > 1.0f) {
+    res = bits_f32(0x7fc00000u);
+    return true;
+  }
+  if (kind != ATANK_ACOS && xf == 0.0f) {
+    res = xf;  // atan(+-0) = asin(+-0) = +-0
+    return true;
+  }
+  if (kind == ATANK_ACOS && xf == 1.0f) {
+    res = 0.0f;
+    return true;
+  }
+  return false;
+}
+
+template <int KIND>
+__device__ __forceinline__ float atan_fast(float xf, const AtanTab& tb, bool& ok) {
+  // atan(2^100) and atan(inf) both round to RN(pi/2): clamp to keep 0 * inf out
+  double x = (double)xf, a = fmin(fabs(x), 0x1p100);
+  double hi, lo, yh;
+  if (KIND == ATANK_ATAN) {
+    atan_ratio_fast(a, 1.0, tb, hi, lo);
+    yh = hi + lo;
+    if (xf < 0.0f) yh = -yh;
+  } else {
+    double s = sqrt(fma(-a, a, 1.0));
+    if (KIND == ATANK_ASIN) {
+      atan_ratio_fast(a, s, tb, hi, lo);
+      yh = hi + lo;
+      if (xf < 0.0f) yh = -yh;
+    } else {
+      atan_ratio_fast(s, a, tb, hi, lo);
+      if (xf < 0.0f) {  // pi - atan(s/|x|)
+        dd p = fast_two_sum(PI_HI, -hi);
+        yh = p.hi + (p.lo + (PI_LO - lo));
+      } else {
+        yh = hi + lo;
+      }
+    }
+  }
+  float res = round_f32_fast<ATAN_LOG2E>(yh, ok);
+  float sp;
+  if (atan_special(xf, KIND, sp)) {
+    res = sp;
+    ok = true;
+  }
+  return res;
+}
+
+// ------------------------------------------------------------ accurate path
+__device__ __forceinline__ dd dd_div_i(dd a, dd b) {
+  double q1 = a.hi / b.hi;
+  dd p = dd_mul_d(b, q1);
+  dd r = dd_add(a, dd_neg(p));
+  double q2 = r.hi / b.hi;
+  return fast_two_sum(q1, q2);
+}
+
+// atan(Y/X) in double-double for double-double Y, X >= 0
+__device__ __forceinline__ dd atan_ratio_acc(dd Y0, dd X0, const AtanTab& tb) {
+  bool inv = Y0.hi > X0.hi;
+  dd Y = inv ? X0 : Y0, X = inv ? Y0 : X0;
+  float zf = (float)Y.hi * __builtin_amdgcn_rcpf((float)X.hi);
+  int j = (int)rintf(16.0f * zf);
+  j = j > 15 ? 15 : (j < 0 ? 0 : j);
+  double c = (double)j * 0.0625;
+  dd num = dd_add(Y, dd_neg(dd_mul_d(X, c)));
+  dd den = dd_add(X, dd_mul_d(Y, c));
+  dd t = dd_div_i(num, den);
+  dd t2 = dd_mul(t, t);
+  double ph = ATAN_TAYLOR[ATAN_TAYLOR_N].x;
+#pragma unroll
+  for (int k = ATAN_TAYLOR_N - 1; k >= 5; k--) ph = fma(ph, t2.hi, ATAN_TAYLOR[k].x);
+  dd p = {ph, 0.0};
+#pragma unroll
+  for (int k = 4; k >= 0; k--) {
+    double2 cc = ATAN_TAYLOR[k];
+    p = dd_add(dd_mul(p, t2), dd{cc.x, cc.y});
+  }
+  dd at = dd_mul(p, t);
+  double4 T = tb.t[j];
+  dd base = inv ? dd{T.z, T.w} : dd{T.x, T.y};
+  return dd_add(base, inv ? dd_neg(at) : at);
+}
+
+// s = sqrt(1 - a^2) as a double-double (a in [0, 1])
+__device__ __forceinline__ dd sqrt_1m_sq(double a) {
+  dd p = two_prod(a, a);
+  dd w = dd_add_d(dd{-p.hi, -p.lo}, 1.0);
+  if (w.hi <= 0.0) return {0.0, 0.0};
+  double s0 = sqrt(w.hi);
+  dd s2 = two_prod(s0, s0);
+  double corr = ((w.hi - s2.hi) - s2.lo + w.lo) / (2.0 * s0);
+  return fast_two_sum(s0, corr);
+}
+
+template <int KIND>
+__device__ __noinline__ AccResult atan_accurate(float xf, const AtanTab& tb) {
+  float sp;
+  if (atan_special(xf, KIND, sp)) return {sp, 1};
+  double a = fmin(fabs((double)xf), 0x1p100);
+  dd y;
+  if (KIND == ATANK_ATAN) {
+    y = atan_ratio_acc(dd{a, 0.0}, dd{1.0, 0.0}, tb);
+    if (xf < 0.0f) y = dd_neg(y);
+  } else {
+    dd s = sqrt_1m_sq(a);
+    if (KIND == ATANK_ASIN) {
+      y = atan_ratio_acc(dd{a, 0.0}, s, tb);
+      if (xf < 0.0f) y = dd_neg(y);
+    } else {
+      y = atan_ratio_acc(s, dd{a, 0.0}, tb);
+      if (xf < 0.0f) y = dd_add(dd{PI_HI, PI_LO}, dd_neg(y));
+    }
+  }
+  bool ok;
+  float r = round_f32_dd(y.hi, y.lo, 0x1p-85, ok);
+  return {r, ok ? 1 : 0};
+}
+
+}  // namespace cr

@@ -1,0 +1,326 @@
+// cr_f32_trig.h -- correctly rounded sinf, cosf, sincosf, tanf (device).
+//
+// Paper, Sec. II-A: the trigonometric kernels branch only for large-argument
+// reduction.  On the GPU every lane runs the same reduction, branch-free:
+// Payne-Hanek (Payne and Hanek, SIGNUM Newsletter 18(1), 1983) in 32-bit
+// integer arithmetic for every |x| >= pi/64.
+//
+//   x = M 2^E (M a 24-bit integer).  N = x 32/pi = M 2^(E+4) sum_i g_i 2^-i
+//   with g_i the bits of 2/pi.  Bits with i <= E - 2 only add multiples of 64
+//   to N, so a 160-bit window W of 2/pi starting at bit E - 1 suffices:
+//   N = M W 2^-154 (mod 64), truncation error < 2^24 2^-154 = 2^-130.
+//   The window is read from a 10-word table (a zero word, then 288 bits of
+//   2/pi) with funnel shifts; the binary point of P = M W is always bit 154.
+//
+//   k = nearest(N), q = k mod 64, f = N - k in [-1/2, 1/2) (64 fraction bits
+//   for the fast path, 128 for the accurate path), r = f pi/32, |r| <= pi/64.
+//   With theta = q pi/32 = quad pi/2 + j pi/32 (j = q mod 16), a 16-entry table
+//   gives sin and cos of j pi/32 (double-double); quadrant symmetries give
+//   sin/cos theta, and
+//       sin x = sin theta cos r + cos theta sin r,
+//       cos x = cos theta cos r - sin theta sin r,   tan x = sin x / cos x.
+//   Near the zeros of sin/cos (j = 0) the table terms are exactly 0 and +-1,
+//   so the result is +-sin r or +-cos r without cancellation.
+#pragma once
+#include "cr_consts.h"
+#include "cr_round.h"
+
+namespace cr {
+
+enum { TRIGK_SIN = 0, TRIGK_COS = 1, TRIGK_TAN = 2, TRIGK_SINCOS = 3 };
+
+struct TrigTab {
+  double4 sc[16];
+  unsigned w[10];
+};
+
+__device__ __forceinline__ void trig_tab_load(TrigTab& t, int tid) {
+  if (tid < 16) t.sc[tid] = SINCOS_T[tid];
+  if (tid < 10) t.w[tid] = TWO_OVER_PI_W[tid];
+}
+
+struct Reduced {
+  int q;                  // k mod 64
+  long long fhi;          // f = (fhi + flo 2^-64) 2^-64, signed
+  unsigned long long flo;
+};
+
+// Payne-Hanek reduction of |x| (ax = its encoding), |x| >= pi/64 and finite;
+// other encodings are clamped to in-range table indices (their result is
+// discarded by the caller).
+__device__ __forceinline__ Reduced payne_hanek(uint32_t ax, const unsigned* w) {
+  int E = (int)(ax >> 23) - 150;
+  E = E < -28 ? -28 : (E > 105 ? 105 : E);
+  uint32_t M = (ax & 0x007fffffu) | 0x00800000u;
+  int sp = E - 2 + 32;  // window start in the zero-prefixed bit string: [2, 135]
+  int wi = sp >> 5, sh = 32 - (sp & 31);
+  uint32_t t0 = w[wi], t1 = w[wi + 1], t2 = w[wi + 2], t3 = w[wi + 3], t4 = w[wi + 4],
+           t5 = w[wi + 5];
+  // W_k = 32 bits of the window (funnel shift; sh = 32 gives the word itself)
+  uint32_t W0 = (uint32_t)((((uint64_t)t0 << 32) | t1) >> sh);
+  uint32_t W1 = (uint32_t)((((uint64_t)t1 << 32) | t2) >> sh);
+  uint32_t W2 = (uint32_t)((((uint64_t)t2 << 32) | t3) >> sh);
+  uint32_t W3 = (uint32_t)((((uint64_t)t3 << 32) | t4) >> sh);
+  uint32_t W4 = (uint32_t)((((uint64_t)t4 << 32) | t5) >> sh);
+  // P = M W, least significant word first (each step is one 32x32+64 multiply-add)
+  uint64_t a = (uint64_t)M * W4;
+  uint32_t p0 = (uint32_t)a;
+  a = (uint64_t)M * W3 + (a >> 32);
+  uint32_t p1 = (uint32_t)a;
+  a = (uint64_t)M * W2 + (a >> 32);
+  uint32_t p2 = (uint32_t)a;
+  a = (uint64_t)M * W1 + (a >> 32);
+  uint32_t p3 = (uint32_t)a;
+  a = (uint64_t)M * W0 + (a >> 32);
+  uint32_t p4 = (uint32_t)a;
+  // integer bits 154..159 = p4[31:26]; fraction bits 153..26
+  uint64_t F = ((uint64_t)(p4 & 0x03ffffffu) << 38) | ((uint64_t)p3 << 6) | (p2 >> 26);
+  uint64_t Fl = ((uint64_t)(p2 & 0x03ffffffu) << 38) | ((uint64_t)p1 << 6) | (p0 >> 26);
+  Reduced R;
+  R.q = (int)(((p4 >> 26) + (uint32_t)(F >> 63)) & 63);  // round to nearest
+  R.fhi = (long long)F;                                   // f - 1 when f >= 1/2
+  R.flo = Fl;
+  return R;
+}
+
+// sin/cos of theta = q pi/32 as double-doubles, from the table and the quadrant
+struct SinCosTheta {
+  double sh, sl, ch, cl;
+};
+
+__device__ __forceinline__ SinCosTheta theta_of(int q, const TrigTab& tb) {
+  double4 T = tb.sc[q & 15];
+  int quad = q >> 4;
+  SinCosTheta r;
+  // quad 0: (S, C); 1: (C, -S); 2: (-S, -C); 3: (-C, S)
+  bool swap = quad & 1;
+  double sh = swap ? T.z : T.x, sl = swap ? T.w : T.y;
+  double ch = swap ? T.x : T.z, cl = swap ? T.y : T.w;
+  bool negs = quad >= 2;
+  bool negc = quad == 1 || quad == 2;
+  r.sh = negs ? -sh : sh;
+  r.sl = negs ? -sl : sl;
+  r.ch = negc ? -ch : ch;
+  r.cl = negc ? -cl : cl;
+  return r;
+}
+
+__device__ __forceinline__ bool trig_special(float xf, float& res, int kind) {
+  if (xf != xf) {
+    res = bits_f32(f32_bits(xf) | 0x00400000u);
+    return true;
+  }
+  if ((f32_bits(xf) & 0x7fffffffu) == 0x7f800000u) {
+    res = bits_f32(0x7fc00000u);
+    return true;
+  }
+  if (xf == 0.0f) {
+    res = kind == TRIGK_COS ? 1.0f : xf;  // sin, tan keep the sign of zero
+    return true;
+  }
+  return false;
+}
+
+// Fast path: binary64 sin and cos of x with absolute error bounds.
+struct TrigFast {
+  double s, c, es, ec;  // values and error bounds
+};
+
+__device__ __forceinline__ TrigFast trig_fast_core(float xf, const TrigTab& tb) {
+  uint32_t ax = f32_bits(xf) & 0x7fffffffu;
+  double axd = (double)bits_f32(ax);
+  bool small = axd < PI64;
+  Reduced R = payne_hanek(ax, tb.w);
+  // f = fhi 2^-64 (+ flo 2^-128, ignored here: < 2^-64)
+  double fh = (double)(R.fhi >> 11) * 0x1p-53;
+  double fl = (double)(R.fhi & 0x7ff) * 0x1p-64;
+  double r = fma(fh, PI32_HI, fma(fh, PI32_MID, fl * PI32_HI));
+  int q = R.q;
+  if (small) {
+    r = axd;
+    q = 0;
+  }
+  double r2 = r * r;
+  double ps = SIN_S[SIN_S_DEG];
+#pragma unroll
+  for (int i = SIN_S_DEG - 1; i >= 0; i--) ps = fma(ps, r2, SIN_S[i]);
+  double pc = COS_C[COS_C_DEG];
+#pragma unroll
+  for (int i = COS_C_DEG - 1; i >= 0; i--) pc = fma(pc, r2, COS_C[i]);
+  double sr = fma(r * r2, ps, r);  // sin r
+  double cm1 = r2 * pc;            // cos r - 1
+  SinCosTheta th = theta_of(q, tb);
+  TrigFast o;
+  o.s = th.sh + (th.sl + fma(th.sh, cm1, th.ch * sr));
+  o.c = th.ch + (th.cl + fma(th.ch, cm1, -(th.sh * sr)));
+  // Error bounds: r is within 2^-52 |r| + 2^-66 of f pi/32 after reduction
+  // (exact when |x| < pi/64); the polynomials are within 2^-66; the sums add
+  // a few units of 2^-53 |result| (|sin x|, |cos x| >= 0.049 unless j = 0, in
+  // which case the table terms are exact).  Bound: 2^-49 |y| + 2^-63.
+  double abs_term = small ? 0.0 : 0x1p-63;
+  o.es = fma(fabs(o.s), 0x1p-49, abs_term);
+  o.ec = fma(fabs(o.c), 0x1p-49, abs_term);
+  return o;
+}
+
+// ------------------------------------------------------------ accurate path
+__device__ __forceinline__ dd dd_div(dd a, dd b) {
+  double q1 = a.hi / b.hi;
+  dd p = dd_mul_d(b, q1);
+  dd r = dd_add(a, dd_neg(p));
+  double q2 = r.hi / b.hi;
+  return fast_two_sum(q1, q2);
+}
+
+// Round h + l to binary32 given an absolute error bound e (accurate path).
+__device__ __forceinline__ float round_f32_dd_abs(double h, double l, double e, bool& ok) {
+  dd lo = fast_two_sum(h, l - e);
+  dd hi = fast_two_sum(h, l + e);
+  float a = (float)ro53(lo.hi, lo.lo);
+  float b = (float)ro53(hi.hi, hi.lo);
+  ok = a == b;
+  return b;
+}
+
+struct TrigAcc {
+  dd s, c;
+  double eabs;  // absolute error bound on each of s, c
+};
+
+// sin x and cos x in double-double: 128-bit reduction, Taylor series of
+// sin r and cos r (|r| <= pi/64; terms of index >= 4 in binary64).
+__device__ __forceinline__ TrigAcc trig_acc_core(float xf, const TrigTab& tb) {
+  uint32_t ax = f32_bits(xf) & 0x7fffffffu;
+  double axd = (double)bits_f32(ax);
+  bool small = axd < PI64;
+  Reduced R = payne_hanek(ax, tb.w);
+  double d1 = (double)(R.fhi >> 11) * 0x1p-53;
+  double d2 = (double)(((uint64_t)(R.fhi & 0x7ff) << 42) | (R.flo >> 22)) * 0x1p-117;
+  double d3 = (double)(R.flo & 0x3fffff) * 0x1p-128;
+  dd f = dd_add_d(fast_two_sum(d1, d2), d3);
+  dd r = dd_mul(f, dd{PI32_HI, PI32_MID});
+  r = dd_add_d(r, f.hi * PI32_LO);
+  int q = R.q;
+  if (small) {
+    r = {axd, 0.0};
+    q = 0;
+  }
+  dd r2 = dd_mul(r, r);
+  double ph = SIN_TAYLOR[TRIG_TAYLOR_N].x;
+#pragma unroll
+  for (int k = TRIG_TAYLOR_N - 1; k >= 4; k--) ph = fma(ph, r2.hi, SIN_TAYLOR[k].x);
+  dd ps = {ph, 0.0};
+#pragma unroll
+  for (int k = 3; k >= 0; k--) {
+    double2 c = SIN_TAYLOR[k];
+    ps = dd_add(dd_mul(ps, r2), dd{c.x, c.y});
+  }
+  dd sr = dd_mul(ps, r);
+  ph = COS_TAYLOR[TRIG_TAYLOR_N].x;
+#pragma unroll
+  for (int k = TRIG_TAYLOR_N - 1; k >= 4; k--) ph = fma(ph, r2.hi, COS_TAYLOR[k].x);
+  dd pc = {ph, 0.0};
+#pragma unroll
+  for (int k = 3; k >= 0; k--) {
+    double2 c = COS_TAYLOR[k];
+    pc = dd_add(dd_mul(pc, r2), dd{c.x, c.y});
+  }
+  SinCosTheta th = theta_of(q, tb);
+  dd S = {th.sh, th.sl}, C = {th.ch, th.cl};
+  TrigAcc o;
+  o.s = dd_add(dd_mul(S, pc), dd_mul(C, sr));
+  o.c = dd_add(dd_mul(C, pc), dd_neg(dd_mul(S, sr)));
+  // reduction: |f| error < 2^-129 (window 2^-130, conversion 2^-130), so r is
+  // within 2^-102 |r| + 2^-132; double-double arithmetic adds < 2^-98 |result|
+  o.eabs = small ? 0.0 : 0x1p-128;
+  return o;
+}
+
+template <int KIND>
+__device__ __noinline__ AccResult trig_accurate(float xf, const TrigTab& tb) {
+  float sp;
+  if (trig_special(xf, sp, KIND)) return {sp, 1};
+  TrigAcc A = trig_acc_core(xf, tb);
+  bool neg = xf < 0.0f;
+  dd y;
+  double e;
+  if (KIND == TRIGK_COS) {
+    y = A.c;
+    e = fma(fabs(y.hi), 0x1p-95, A.eabs);
+  } else if (KIND == TRIGK_SIN) {
+    y = neg ? dd_neg(A.s) : A.s;
+    e = fma(fabs(y.hi), 0x1p-95, A.eabs);
+  } else {
+    y = dd_div(A.s, A.c);
+    if (neg) y = dd_neg(y);
+    // relative errors of s and c add; the absolute parts scale with 1/|c|
+    double ic = 1.0 / fabs(A.c.hi);
+    e = fma(fabs(y.hi), 0x1p-93, A.eabs * ic * (1.0 + fabs(y.hi)) * 2.0);
+  }
+  bool ok;
+  float r = round_f32_dd_abs(y.hi, y.lo, e, ok);
+  return {r, ok ? 1 : 0};
+}
+
+// sincos accurate path: both results (sin in r, cos in r2)
+struct AccResult2 {
+  float s, c;
+  int ok;
+};
+
+__device__ __noinline__ AccResult2 sincos_accurate(float xf, const TrigTab& tb) {
+  float ss, cs;
+  if (trig_special(xf, ss, TRIGK_SIN)) {
+    trig_special(xf, cs, TRIGK_COS);
+    return {ss, cs, 1};
+  }
+  TrigAcc A = trig_acc_core(xf, tb);
+  dd s = xf < 0.0f ? dd_neg(A.s) : A.s;
+  bool ok1, ok2;
+  float rs = round_f32_dd_abs(s.hi, s.lo, fma(fabs(s.hi), 0x1p-95, A.eabs), ok1);
+  float rc = round_f32_dd_abs(A.c.hi, A.c.lo, fma(fabs(A.c.hi), 0x1p-95, A.eabs), ok2);
+  return {rs, rc, (ok1 && ok2) ? 1 : 0};
+}
+
+template <int KIND>
+__device__ __forceinline__ float trig_fast(float xf, const TrigTab& tb, bool& ok) {
+  TrigFast F = trig_fast_core(xf, tb);
+  bool neg = xf < 0.0f;
+  float res;
+  if (KIND == TRIGK_COS) {
+    res = round_f32_fast_abs(F.c, F.ec, ok);
+  } else if (KIND == TRIGK_SIN) {
+    res = round_f32_fast_abs(neg ? -F.s : F.s, F.es, ok);
+  } else {
+    double t = F.s / F.c;
+    // relative error of the quotient plus the absolute errors of s and c
+    // magnified by 1/|c|: |dt| <= |t| 2^-52 + (es + |t| ec) / |c|
+    double ic = __builtin_amdgcn_rcp(fabs(F.c));
+    double e = fma(fabs(t), 0x1p-50, (F.es + fabs(t) * F.ec) * ic * 2.0);
+    res = round_f32_fast_abs(neg ? -t : t, e, ok);
+  }
+  float sp;
+  if (trig_special(xf, sp, KIND)) {
+    res = sp;
+    ok = true;
+  }
+  return res;
+}
+
+// sincos fast path: returns sin in the result, cos in *c
+__device__ __forceinline__ float sincos_fast(float xf, const TrigTab& tb, float& c, bool& ok) {
+  TrigFast F = trig_fast_core(xf, tb);
+  bool ok1, ok2;
+  float s = round_f32_fast_abs(xf < 0.0f ? -F.s : F.s, F.es, ok1);
+  c = round_f32_fast_abs(F.c, F.ec, ok2);
+  ok = ok1 && ok2;
+  float sp;
+  if (trig_special(xf, sp, TRIGK_SIN)) {
+    s = sp;
+    trig_special(xf, c, TRIGK_COS);
+    ok = true;
+  }
+  return s;
+}
+
+}  // namespace cr

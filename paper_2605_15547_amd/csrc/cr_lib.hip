@@ -17,6 +17,9 @@
 #include "cr_f32_exp.h"
 #include "cr_f32_log.h"
 #include "cr_f32_rsqrt.h"
+#include "cr_f32_trig.h"
+#include "cr_f32_atan.h"
+#include "cr_f32_hyp.h"
 
 using namespace cr;
 
@@ -90,6 +93,42 @@ struct OpRsqrt {
   static __device__ __noinline__ AccResult accurate(float x, const Tab&) {
     bool ok;
     return {rsqrt_fast(x, ok), 1};
+  }
+};
+
+template <int KIND>
+struct OpTrig {
+  using Tab = TrigTab;
+  static __device__ __forceinline__ void load(Tab& t, int tid) { trig_tab_load(t, tid); }
+  static __device__ __forceinline__ float fast(float x, const Tab& t, bool& ok) {
+    return trig_fast<KIND>(x, t, ok);
+  }
+  static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
+    return trig_accurate<KIND>(x, t);
+  }
+};
+
+template <int KIND>
+struct OpAtan {
+  using Tab = AtanTab;
+  static __device__ __forceinline__ void load(Tab& t, int tid) { atan_tab_load(t, tid); }
+  static __device__ __forceinline__ float fast(float x, const Tab& t, bool& ok) {
+    return atan_fast<KIND>(x, t, ok);
+  }
+  static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
+    return atan_accurate<KIND>(x, t);
+  }
+};
+
+template <int KIND>
+struct OpHyp {
+  using Tab = ExpTab;
+  static __device__ __forceinline__ void load(Tab& t, int tid) { exp_tab_load(t, tid); }
+  static __device__ __forceinline__ float fast(float x, const Tab& t, bool& ok) {
+    return hyp_fast<KIND>(x, t, ok);
+  }
+  static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
+    return hyp_accurate<KIND>(x, t);
   }
 };
 
@@ -271,6 +310,139 @@ __global__ void __launch_bounds__(BLOCK)
   }
 }
 
+// sincosf: the map kernel with two planar outputs (sin block, cos block), both
+// 16-byte aligned (the host checks; otherwise the scalar form below runs).
+__device__ __noinline__ void flush_queue_sincos(Deferred& q, const TrigTab& tab, float* os,
+                                                float* oc, DevStats* st, long long elem_base) {
+  unsigned n = q.n < QCAP ? q.n : QCAP;
+  for (unsigned k = threadIdx.x; k < n; k += BLOCK) {
+    AccResult2 a = sincos_accurate(q.x[k], tab);
+    os[q.idx[k]] = a.s;
+    oc[q.idx[k]] = a.c;
+    if (!a.ok) {
+      atomicAdd(&q.esc, 1u);
+      note_escape(st, elem_base + q.idx[k]);
+    }
+  }
+  if (threadIdx.x == 0) {
+    q.lanes += n;
+    q.waves += (n + 63) / 64;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) q.n = 0;
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    k_map_sincos(const float4* in, float4* outs, float4* outc, long long n4, DevStats* st,
+                 unsigned flags, long long elem_base) {
+  __shared__ TrigTab tab;
+  __shared__ Deferred q;
+  trig_tab_load(tab, threadIdx.x);
+  if (threadIdx.x == 0) {
+    q.n = 0;
+    q.lanes = q.waves = q.esc = 0;
+  }
+  __syncthreads();
+  const bool force = flags & CR_FLAG_FORCE_FALLBACK;
+  const long long ntiles = (n4 + BLOCK * TILE_U - 1) / (BLOCK * TILE_U);
+  int iter = 0;
+  for (long long t = blockIdx.x; t < ntiles; t += gridDim.x, iter++) {
+    long long base = t * (BLOCK * TILE_U) + threadIdx.x;
+    float4 v[TILE_U], c4[TILE_U];
+#pragma unroll
+    for (int u = 0; u < TILE_U; u++) {
+      long long i = base + (long long)u * BLOCK;
+      if (i < n4) v[u] = in[i];
+    }
+#pragma unroll
+    for (int u = 0; u < TILE_U; u++) {
+      long long i = base + (long long)u * BLOCK;
+      if (i < n4) {
+        float* e = reinterpret_cast<float*>(&v[u]);
+        float* ec = reinterpret_cast<float*>(&c4[u]);
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+          bool ok;
+          float x = e[c];
+          e[c] = sincos_fast(x, tab, ec[c], ok);
+          if (!ok || force) {
+            unsigned pos = atomicAdd(&q.n, 1u);
+            if (pos < QCAP) {
+              q.idx[pos] = (unsigned)(4 * i + c);
+              q.x[pos] = x;
+            } else {
+              AccResult2 a = sincos_accurate(x, tab);
+              e[c] = a.s;
+              ec[c] = a.c;
+              atomicAdd(&q.lanes, 1u);
+              if (!a.ok) {
+                atomicAdd(&q.esc, 1u);
+                note_escape(st, elem_base + 4 * i + c);
+              }
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TILE_U; u++) {
+      long long i = base + (long long)u * BLOCK;
+      if (i < n4) {
+        outs[i] = v[u];
+        outc[i] = c4[u];
+      }
+    }
+    if (iter % QCHECK == QCHECK - 1) {
+      __syncthreads();
+      const unsigned nq = q.n;
+      __syncthreads();
+      if (nq > QFLUSH)
+        flush_queue_sincos(q, tab, reinterpret_cast<float*>(outs), reinterpret_cast<float*>(outc),
+                           st, elem_base);
+    }
+  }
+  __syncthreads();
+  if (q.n)
+    flush_queue_sincos(q, tab, reinterpret_cast<float*>(outs), reinterpret_cast<float*>(outc), st,
+                       elem_base);
+  if (threadIdx.x == 0 && q.lanes) {
+    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
+    atomicAdd(&c.fallback_lanes, (unsigned long long)q.lanes);
+    atomicAdd(&c.fallback_waves, (unsigned long long)q.waves);
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    k_map_sincos_scalar(const float* in, float* outs, float* outc, long long n, DevStats* st,
+                        unsigned flags, long long elem_base) {
+  __shared__ TrigTab tab;
+  trig_tab_load(tab, threadIdx.x);
+  __syncthreads();
+  const bool force = flags & CR_FLAG_FORCE_FALLBACK;
+  unsigned lanes = 0;
+  for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n;
+       i += (long long)gridDim.x * BLOCK) {
+    bool ok;
+    float x = in[i], c;
+    float s = sincos_fast(x, tab, c, ok);
+    if (!ok || force) {
+      AccResult2 a = sincos_accurate(x, tab);
+      s = a.s;
+      c = a.c;
+      lanes++;
+      if (!a.ok) note_escape(st, elem_base + i);
+    }
+    outs[i] = s;
+    outc[i] = c;
+  }
+  if (lanes) {
+    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
+    atomicAdd(&c.fallback_lanes, (unsigned long long)lanes);
+    atomicAdd(&c.fallback_waves, 1ull);
+  }
+}
+
 __global__ void k_zero_stats(DevStats* st) {
   unsigned long long* p = reinterpret_cast<unsigned long long*>(st);
   for (int i = threadIdx.x; i < (int)(sizeof(DevStats) / 8); i += blockDim.x) p[i] = 0;
@@ -369,8 +541,40 @@ int launch_map_f32(const float* in, float* out, size_t n, hipStream_t s, unsigne
   return CR_OK;
 }
 
+int launch_sincos(const float* in, float* out, size_t n, hipStream_t s, unsigned flags,
+                  DevStats* st) {
+  float* outc = out + n;
+  uintptr_t ai = (uintptr_t)in, ao = (uintptr_t)out, ac = (uintptr_t)outc;
+  bool vec = (ai & 15) == 0 && (ao & 15) == 0 && (ac & 15) == 0;
+  size_t body4 = vec ? n / 4 : 0;
+  size_t done4 = 0;
+  while (done4 < body4) {
+    size_t chunk4 = body4 - done4;
+    if (chunk4 > ((size_t)1 << 29)) chunk4 = (size_t)1 << 29;
+    size_t tiles = (chunk4 + BLOCK * TILE_U - 1) / (BLOCK * TILE_U);
+    size_t g = tiles < (size_t)grid_blocks() ? tiles : (size_t)grid_blocks();
+    size_t off = 4 * done4;
+    hipLaunchKernelGGL(k_map_sincos, dim3((unsigned)g), dim3(BLOCK), 0, s,
+                       reinterpret_cast<const float4*>(in + off),
+                       reinterpret_cast<float4*>(out + off), reinterpret_cast<float4*>(outc + off),
+                       (long long)chunk4, st, flags, (long long)off);
+    done4 += chunk4;
+  }
+  size_t off = 4 * body4;
+  if (off < n) {
+    size_t rest = n - off;
+    size_t g = (rest + BLOCK - 1) / BLOCK;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_map_sincos_scalar, dim3((unsigned)g), dim3(BLOCK), 0, s, in + off,
+                       out + off, outc + off, (long long)rest, st, flags, (long long)off);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e);
+  return CR_OK;
+}
+
 bool func_valid(int f) { return (f >= 0 && f < CR_NUM_F32) || f == CR_EXP || f == CR_LOG; }
-bool func_built(int f) { return f >= CR_EXPF && f <= CR_RSQRTF; }
+bool func_built(int f) { return f >= CR_EXPF && f <= CR_TANHF; }
 
 int dispatch_f32(int f, const float* in, float* out, size_t n, hipStream_t s, unsigned flags,
                  DevStats* st) {
@@ -384,6 +588,16 @@ int dispatch_f32(int f, const float* in, float* out, size_t n, hipStream_t s, un
     case CR_LOG10F: return launch_map_f32<OpLog<LOGK_10>>(in, out, n, s, flags, st);
     case CR_LOG1PF: return launch_map_f32<OpLog<LOGK_1P>>(in, out, n, s, flags, st);
     case CR_RSQRTF: return launch_map_f32<OpRsqrt>(in, out, n, s, flags, st);
+    case CR_SINF: return launch_map_f32<OpTrig<TRIGK_SIN>>(in, out, n, s, flags, st);
+    case CR_COSF: return launch_map_f32<OpTrig<TRIGK_COS>>(in, out, n, s, flags, st);
+    case CR_TANF: return launch_map_f32<OpTrig<TRIGK_TAN>>(in, out, n, s, flags, st);
+    case CR_SINCOSF: return launch_sincos(in, out, n, s, flags, st);
+    case CR_ASINF: return launch_map_f32<OpAtan<ATANK_ASIN>>(in, out, n, s, flags, st);
+    case CR_ACOSF: return launch_map_f32<OpAtan<ATANK_ACOS>>(in, out, n, s, flags, st);
+    case CR_ATANF: return launch_map_f32<OpAtan<ATANK_ATAN>>(in, out, n, s, flags, st);
+    case CR_SINHF: return launch_map_f32<OpHyp<HYPK_SINH>>(in, out, n, s, flags, st);
+    case CR_COSHF: return launch_map_f32<OpHyp<HYPK_COSH>>(in, out, n, s, flags, st);
+    case CR_TANHF: return launch_map_f32<OpHyp<HYPK_TANH>>(in, out, n, s, flags, st);
   }
   return CR_E_FUNC;
 }

@@ -262,6 +262,108 @@ def gen_log():
     emit()
 
 
+# =================================================================== trig family
+def gen_trig():
+    emit("// ---- trigonometric family (sinf, cosf, sincosf, tanf) ----")
+    # 2/pi = sum g_i 2^-i; word k (k >= 1) holds bits 32(k-1)+1 .. 32k; word 0 is
+    # zero so that windows may start before the binary point
+    words = [0]
+    with mp.workprec(800):  # 288 table bits need far more than the default precision
+        two_over_pi = 2 / mp.pi
+        for k in range(1, 10):
+            words.append(int(mp.floor(two_over_pi * mp.mpf(2) ** (32 * k))) & 0xFFFFFFFF)
+    emit("// bits of 2/pi: word k (k >= 1) = bits 32(k-1)+1 .. 32k; word 0 = 0")
+    emit("__device__ __constant__ const unsigned TWO_OVER_PI_W[10] = {%s};"
+         % ", ".join("0x%08xu" % w for w in words))
+    h, m1, l = td(mp.pi / 32)
+    emit_const("PI32_HI", h, "pi/32")
+    emit_const("PI32_MID", m1)
+    emit_const("PI32_LO", l)
+    emit_const("PI64", d(mp.pi / 64), "pi/64 (small-argument threshold)")
+    emit("// sin(j pi/32), cos(j pi/32) for j = 0..15, double-double: {s_hi, s_lo, c_hi, c_lo}")
+    emit("__device__ __constant__ const double4 SINCOS_T[16] = {")
+    for j in range(16):
+        sh, sl = dd(mp.sin(j * mp.pi / 32))
+        ch, cl = dd(mp.cos(j * mp.pi / 32))
+        emit("  {%s, %s, %s, %s}," % (hexd(sh), hexd(sl), hexd(ch), hexd(cl)))
+    emit("};")
+    rho = mp.pi / 64 * mp.mpf("1.0001")
+    # sin r = r + r^3 S(r^2); cos r - 1 = r^2 C(r^2)
+    for name, g, w, lo_deg in (
+            ("SIN_S", lambda u: (mp.sin(mp.sqrt(u)) / mp.sqrt(u) - 1) / u if u != 0 else mp.mpf(-1) / 6,
+             lambda u: u * mp.sqrt(u), 2),
+            ("COS_C", lambda u: (mp.cos(mp.sqrt(u)) - 1) / u if u != 0 else mp.mpf(-1) / 2,
+             lambda u: u, 2)):
+        for deg in range(lo_deg, 7):
+            cs = lawson_fit(g, w, mp.mpf(0), rho * rho, list(range(deg + 1)), npts=120, iters=16)
+            cd = [d(v) for v in cs]
+            if name == "SIN_S":
+                err = max_err(lambda r: mp.sin(r) - r - r ** 3 * sum(mp.mpf(cd[k]) * r ** (2 * k)
+                                                                       for k in range(len(cd))),
+                              mp.mpf(0), rho)
+            else:
+                err = max_err(lambda r: mp.cos(r) - 1 - r ** 2 * sum(mp.mpf(cd[k]) * r ** (2 * k)
+                                                                      for k in range(len(cd))),
+                              mp.mpf(0), rho)
+            if err < mp.mpf(2) ** -66:
+                break
+        bound = err * mp.mpf("1.25")
+        emit("// %s: |r| <= pi/64; |approximation error| <= 2^%.2f (absolute)"
+             % ("sin r = r + r^3 S(r^2)" if name == "SIN_S" else "cos r - 1 = r^2 C(r^2)",
+                log2_of(bound)))
+        emit_arr(name, cd, "coefficients (degree %d in r^2)" % (len(cd) - 1))
+        emit("#define %s_DEG %d" % (name, len(cd) - 1))
+    # accurate path: Taylor coefficients (-1)^k / (2k+1)! and (-1)^k / (2k)!
+    N = 9
+    emit("#define TRIG_TAYLOR_N %d" % N)
+    emit_dd_table("SIN_TAYLOR", [(-1) ** k / mp.factorial(2 * k + 1) for k in range(N + 1)],
+                  "(-1)^k/(2k+1)!  (|r| <= pi/64: the omitted terms are below 2^-120 |r|)")
+    emit_dd_table("COS_TAYLOR", [(-1) ** k / mp.factorial(2 * k) for k in range(N + 1)],
+                  "(-1)^k/(2k)!")
+    emit()
+
+
+# ============================================================= inverse trig family
+def gen_atan():
+    emit("// ---- inverse trigonometric family (atanf, asinf, acosf) ----")
+    emit("// {atan(j/16) hi, lo, (pi/2 - atan(j/16)) hi, lo}, j = 0..15")
+    emit("__device__ __constant__ const double4 ATAN_T[16] = {")
+    for j in range(16):
+        a = mp.atan(mp.mpf(j) / 16)
+        ah, al = dd(a)
+        bh, bl = dd(mp.pi / 2 - a)
+        emit("  {%s, %s, %s, %s}," % (hexd(ah), hexd(al), hexd(bh), hexd(bl)))
+    emit("};")
+    h, l = dd(mp.pi)
+    emit_const("PI_HI", h)
+    emit_const("PI_LO", l)
+    h, l = dd(mp.pi / 2)
+    emit_const("PIO2_HI", h)
+    emit_const("PIO2_LO", l)
+    # |t| <= (1/2)/(16 + 15/16) < 0.0296 for y <= x; the other branch is
+    # symmetric; 1/31 covers both with margin
+    rho = mp.mpf(1) / 31
+    for deg in range(3, 8):
+        cs = lawson_fit(lambda u: (mp.atan(mp.sqrt(u)) / mp.sqrt(u) - 1) / u if u != 0 else mp.mpf(-1) / 3,
+                        lambda u: u * mp.sqrt(u), mp.mpf(0), rho * rho, list(range(deg + 1)),
+                        npts=120, iters=16)
+        cd = [d(v) for v in cs]
+        err = max_err(lambda t: mp.atan(t) - t - t ** 3 * sum(mp.mpf(cd[k]) * t ** (2 * k)
+                                                               for k in range(len(cd))),
+                      mp.mpf(0), rho)
+        if err < mp.mpf(2) ** -66:
+            break
+    emit("// atan t = t + t^3 P(t^2), |t| <= 1/31; |error| <= 2^%.2f (absolute)"
+         % log2_of(err * mp.mpf("1.25")))
+    emit_arr("ATAN_P", cd, "coefficients (degree %d in t^2)" % (len(cd) - 1))
+    emit("#define ATAN_P_DEG %d" % (len(cd) - 1))
+    N = 12
+    emit("#define ATAN_TAYLOR_N %d" % N)
+    emit_dd_table("ATAN_TAYLOR", [mp.mpf(-1) ** k / (2 * k + 1) for k in range(N + 1)],
+                  "(-1)^k/(2k+1)  (|t| <= 1/31: omitted terms below 2^-125 |t|)")
+    emit()
+
+
 def main():
     emit("// Generated by paper_2605_15547_amd/gen/gen_consts.py -- do not edit.")
     emit("// Tables and polynomial coefficients of the correctly rounded kernels.")
@@ -270,6 +372,8 @@ def main():
     emit()
     gen_exp()
     gen_log()
+    gen_trig()
+    gen_atan()
     with open(OUT, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("wrote", OUT)
