@@ -92,6 +92,47 @@ int cr_eval_ex(int func_id, int impl, unsigned flags, const void *in, void *out,
  * build of the library, else 0. */
 int cr_available(int func_id, int impl);
 
+/* ------------------------------------------------------------------ batches
+ * Many requests of mixed function and uneven length evaluated by ONE
+ * persistent kernel launch, captured once in a HIP graph (the batched form of
+ * the elementwise map; the paper's SIMD functions are called on vectors of
+ * arbitrary length, Sec. III-A).  Requests follow the conventions above
+ * (device pointers, element alignment, sincosf planar within its own output,
+ * in place allowed except for sincosf); binary32 functions only (ids 0..18);
+ * each request holds fewer than 2^31 elements.  Requests may not overlap
+ * each other's outputs (not checked across requests).
+ */
+typedef struct {
+  int32_t func_id; /* enum cr_func, 0..18 */
+  int32_t impl;    /* enum cr_impl */
+  const void *in;  /* device pointer, n elements */
+  void *out;       /* device pointer, n (2n for sincosf) elements */
+  int64_t n;
+} cr_request;
+
+typedef struct cr_batch_plan cr_batch_plan; /* opaque, owned by the library */
+
+/* Validate the requests, upload the tile table and capture the launch in a
+ * HIP graph.  The plan keeps the request pointers: the buffers must stay
+ * valid while the plan is launched.  flags: enum cr_flag (applied to every
+ * request).  On success *plan receives a new plan (free it with
+ * cr_batch_plan_destroy); on error *plan is NULL and nothing is allocated.
+ * Errors: CR_E_NULL (reqs or plan NULL, or a NULL pointer in a request with
+ * n > 0), CR_E_FUNC, CR_E_IMPL, CR_E_ALIGN, CR_E_OVERLAP (within a request),
+ * CR_E_SIZE (num < 0 or a request with n < 0 or n >= 2^31), CR_E_NOMEM,
+ * CR_E_HIP. */
+int cr_batch_plan_create(const cr_request *reqs, int32_t num, unsigned flags,
+                         cr_batch_plan **plan);
+/* Launch the plan's graph on the stream (asynchronous, stream-ordered). */
+int cr_batch_plan_launch(cr_batch_plan *plan, void *stream);
+/* Release the plan (synchronises with its last launch first). */
+int cr_batch_plan_destroy(cr_batch_plan *plan);
+/* Evaluate the requests with one launch on the stream, without a graph.  The
+ * request and tile tables are allocated and freed stream-ordered; the call
+ * synchronises the stream once, after copying the tables from host memory
+ * and before the launch. */
+int cr_eval_batch(const cr_request *reqs, int32_t num, void *stream);
+
 /* Per-device counters of the current device, cumulative since the last reset
  * (paper, Sec. III-B: the cost of lanes sent to the accurate path).
  *   elems          elements submitted through cr_eval / cr_eval_ex

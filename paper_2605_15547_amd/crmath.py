@@ -24,14 +24,21 @@ CR_OK = 0
 STATUS = {0: "CR_OK", -1: "CR_E_FUNC", -2: "CR_E_NULL", -3: "CR_E_OVERLAP", -4: "CR_E_ALIGN",
           -5: "CR_E_IMPL", -6: "CR_E_HIP", -7: "CR_E_NOMEM", -9: "CR_E_SIZE"}
 
-EXPORTED = ["cr_eval", "cr_eval_ex", "cr_available", "cr_stats_reset", "cr_stats_read",
-            "cr_status_str", "cr_last_hip_error"]
+EXPORTED = ["cr_eval", "cr_eval_ex", "cr_available", "cr_batch_plan_create",
+            "cr_batch_plan_launch", "cr_batch_plan_destroy", "cr_eval_batch", "cr_stats_reset",
+            "cr_stats_read", "cr_status_str", "cr_last_hip_error"]
 
 
 class CrError(RuntimeError):
     def __init__(self, status, what):
         self.status = status
         super().__init__("%s: %s (%d)" % (what, STATUS.get(status, "?"), status))
+
+
+class Request(ctypes.Structure):
+    """cr_request: one entry of a batch (device pointers as integers)."""
+    _fields_ = [("func_id", ctypes.c_int32), ("impl", ctypes.c_int32),
+                ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p), ("n", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -58,6 +65,11 @@ def lib():
         L.cr_eval_ex.restype = ctypes.c_int
         L.cr_available.argtypes = [ctypes.c_int, ctypes.c_int]
         L.cr_available.restype = ctypes.c_int
+        L.cr_batch_plan_create.argtypes = [ctypes.POINTER(Request), ctypes.c_int32, ctypes.c_uint,
+                                           ctypes.POINTER(ctypes.c_void_p)]
+        L.cr_batch_plan_launch.argtypes = [vp, vp]
+        L.cr_batch_plan_destroy.argtypes = [vp]
+        L.cr_eval_batch.argtypes = [ctypes.POINTER(Request), ctypes.c_int32, vp]
         L.cr_stats_reset.argtypes = [vp]
         L.cr_stats_read.argtypes = [vp, ctypes.POINTER(Stats)]
         L.cr_status_str.argtypes = [ctypes.c_int]
@@ -103,6 +115,50 @@ def evaluate(func, x, out=None, impl=IMPL_AUTO, flags=0, stream=None):
         out = torch.empty(nout, dtype=want, device=x.device)
     eval_ptr(fid, x.data_ptr(), out.data_ptr(), n, impl, flags, _stream_ptr(stream))
     return out.view(2, n) if fid == FUNC_ID["sincosf"] else out.view(x.shape)
+
+
+def _requests(reqs):
+    """reqs: list of (func, in_ptr, out_ptr, n[, impl]) -> ctypes array"""
+    arr = (Request * max(1, len(reqs)))()
+    for i, r in enumerate(reqs):
+        func, ip, op, n = r[:4]
+        impl = r[4] if len(r) > 4 else IMPL_AUTO
+        arr[i] = Request(_fid(func), impl, ip, op, n)
+    return arr
+
+
+class BatchPlan:
+    """A cr_batch_plan: requests captured into one graph launch."""
+
+    def __init__(self, reqs, flags=0):
+        self._arr = _requests(reqs)
+        self.handle = ctypes.c_void_p()
+        rc = lib().cr_batch_plan_create(self._arr, len(reqs), flags, ctypes.byref(self.handle))
+        if rc != CR_OK:
+            raise CrError(rc, "cr_batch_plan_create")
+
+    def launch(self, stream=None):
+        rc = lib().cr_batch_plan_launch(self.handle, _stream_ptr(stream))
+        if rc != CR_OK:
+            raise CrError(rc, "cr_batch_plan_launch")
+
+    def destroy(self):
+        if self.handle:
+            lib().cr_batch_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def eval_batch(reqs, stream=None):
+    arr = _requests(reqs)
+    rc = lib().cr_eval_batch(arr, len(reqs), _stream_ptr(stream))
+    if rc != CR_OK:
+        raise CrError(rc, "cr_eval_batch")
 
 
 def stats_reset(stream=None):

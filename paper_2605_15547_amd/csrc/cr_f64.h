@@ -1,0 +1,251 @@
+// cr_f64.h -- correctly rounded binary64 exp and log (device).
+//
+// Paper, Sec. II-B: a highly accurate SIMD main path, a correct rounding
+// test, and a slower path for the lanes that fail it; the paper's cr_exp2
+// uses three 16-entry double-double tables and its cr_log one 128-entry
+// table.  This library provides exp and log with 16-entry tables only:
+//
+// exp: k = nearest(x 256/ln2), r = x - k ln2/256 (four-part Cody-Waite,
+//   |r| <= ln2/512), k = 256 m + 16 i + j, e^x = 2^m T1[i] T2[j] e^r with
+//   T1 = 2^(i/16), T2 = 2^(j/256) (double-double in the main path, triple-
+//   double in the accurate path).  Subnormal results are rounded at the fixed
+//   quantum 2^-1074 by rounding y 2^(m+1074) to an integer; overflow comes
+//   from scaling the rounded value.
+// log: x = 2^e' m, m in [0.75, 1.5) (subnormal x scaled by 2^64 first), the
+//   same 16-entry 9-bit reciprocal table as binary32: t = m c_j - 1 exact as a
+//   double-double (TwoProd), log x = e' ln2 - ln c_j + log1p(t) with
+//   log1p t = t - t^2/2 + t^3/3 + t^4 S(t) (main path) or 2 atanh(t/(2+t))
+//   (accurate path, triple-double).
+#pragma once
+#include "cr_consts.h"
+#include "cr_round.h"
+#include "cr_td.h"
+
+namespace cr {
+
+struct Exp64Tab {
+  double4 t1[16], t2[16];
+};
+struct Log64Tab {
+  double c[16];
+  double4 L[16];
+};
+
+__device__ __forceinline__ void exp64_tab_load(Exp64Tab& t, int tid) {
+  if (tid < 16) {
+    t.t1[tid] = EXP64_T1[tid];
+    t.t2[tid] = EXP64_T2[tid];
+  }
+}
+__device__ __forceinline__ void log64_tab_load(Log64Tab& t, int tid) {
+  if (tid < 16) {
+    t.c[tid] = LOG_C[tid];
+    t.L[tid] = LOG64_L[tid];
+  }
+}
+
+// ------------------------------------------------------------------- exp
+__device__ __forceinline__ bool exp64_special(double x, double& res) {
+  if (x != x) {
+    res = __longlong_as_double(__double_as_longlong(x) | 0x0008000000000000ll);
+    return true;
+  }
+  if (x == 0.0) {
+    res = 1.0;
+    return true;
+  }
+  return false;
+}
+
+// main-path error: q within 2^-71, tables 2^-104, products and sum 2^-104:
+// the test uses 2^-66 |y| (relative)
+constexpr double EXP64_EPS = 0x1p-66;
+
+__device__ __forceinline__ double exp64_fast(double x, const Exp64Tab& tb, bool& ok) {
+  double xc = fmin(fmax(x, -746.0), 710.0);  // beyond: 0 or +inf after scaling
+  double kd = rint(xc * EXP64_INV);
+  int k = (int)kd;
+  double r0 = fma(-kd, EXP64_C1, xc);  // exact: |k| < 2^19, C1 has 34 bits
+  dd p = two_prod(kd, EXP64_C2);
+  dd s = two_sum(r0, -p.hi);
+  dd r = fast_two_sum(s.hi, (s.lo - p.lo) - kd * EXP64_C3);
+  double pp = EXP64_P[EXP64_P_DEG];
+#pragma unroll
+  for (int i = EXP64_P_DEG - 1; i >= 0; i--) pp = fma(pp, r.hi, EXP64_P[i]);
+  dd q = fast_two_sum(r.hi, fma(r.hi * r.hi, pp, r.lo));  // e^r - 1
+  int m = k >> 8;
+  double4 A = tb.t1[(k >> 4) & 15], B = tb.t2[k & 15];
+  dd T = dd_mul(dd{A.x, A.y}, dd{B.x, B.y});
+  dd y = dd_add(T, dd_mul(T, q));  // T e^r, in [2^-1/512, 2)
+  double res;
+  double e = fabs(y.hi) * EXP64_EPS;
+  if (m >= -1021) {  // normal result: round in the unscaled domain, then scale
+    double a = y.hi + (y.lo - e);
+    double b = y.hi + (y.lo + e);
+    ok = a == b;
+    res = scale_pow2(b, m);
+  } else {  // subnormal (or zero) result: round y 2^(m+1074) to an integer
+    // (y 2^(m+1074) < 2^53; for m + 1074 < 0 it is below 1 and rounds to 0 or 1)
+    double sc = pow2i(m + 1074 > -200 ? m + 1074 : -200);
+    double n = round_to_int(y.hi * sc, y.lo * sc, 0.0, e * sc, ok);
+    res = n * 0x1p-1074;
+  }
+  double sp;
+  if (exp64_special(x, sp)) {
+    res = sp;
+    ok = true;
+  }
+  return res;
+}
+
+struct AccResultD {
+  double r;
+  int ok;
+};
+
+__device__ __noinline__ AccResultD exp64_accurate(double x, const Exp64Tab& tb) {
+  double sp;
+  if (exp64_special(x, sp)) return {sp, 1};
+  double xc = fmin(fmax(x, -746.0), 710.0);
+  double kd = rint(xc * EXP64_INV);
+  int k = (int)kd;
+  // r = x - k (C1 + C2 + C3 + C4) as a triple-double
+  td r = td_from(fma(-kd, EXP64_C1, xc));
+  dd p2 = two_prod(kd, EXP64_C2);
+  dd p3 = two_prod(kd, EXP64_C3);
+  r = td_add(r, td{-p2.hi, -p2.lo, 0.0});
+  r = td_add(r, td{-p3.hi, -p3.lo, -kd * EXP64_C4});
+  // e^r - 1: Taylor to degree 13 (|r| <= ln2/512: remainder < 2^-150);
+  // degrees 6.. in double-double, 1..5 in triple-double
+  dd rd = {r.h, r.m};
+  dd ph = {INV_FACT[13].x, INV_FACT[13].y};
+#pragma unroll
+  for (int i = 12; i >= 6; i--) ph = dd_add(dd_mul(ph, rd), dd{INV_FACT[i].x, INV_FACT[i].y});
+  td pt = td_from_dd(ph);
+#pragma unroll
+  for (int i = 5; i >= 1; i--) pt = td_add(td_mul(pt, r), td_ld(INV_FACT_TD[i]));
+  td q = td_mul(pt, r);
+  int m = k >> 8;
+  td T = td_mul(td_ld(tb.t1[(k >> 4) & 15]), td_ld(tb.t2[k & 15]));
+  td y = td_add(T, td_mul(T, q));
+  double e = fabs(y.h) * 0x1p-135;
+  bool ok;
+  double res;
+  if (m >= -1021) {
+    double c = round64_tail(y.h, y.m, y.l, e, ok);
+    res = scale_pow2(c, m);
+  } else {
+    double sc = pow2i(m + 1074 > -200 ? m + 1074 : -200);
+    double n = round_to_int(y.h * sc, y.m * sc, y.l * sc, e * sc, ok);
+    res = n * 0x1p-1074;
+  }
+  return {res, ok ? 1 : 0};
+}
+
+// ------------------------------------------------------------------- log
+__device__ __forceinline__ bool log64_special(double x, double& res) {
+  if (x != x) {
+    res = __longlong_as_double(__double_as_longlong(x) | 0x0008000000000000ll);
+    return true;
+  }
+  if (x == 0.0) {
+    res = -INFINITY;
+    return true;
+  }
+  if (x < 0.0) {
+    res = __longlong_as_double(0x7ff8000000000000ll);
+    return true;
+  }
+  if (x == INFINITY) {
+    res = INFINITY;
+    return true;
+  }
+  if (x == 1.0) {
+    res = 0.0;
+    return true;
+  }
+  return false;
+}
+
+struct Log64Setup {
+  double m, c;
+  int e2, j;
+};
+
+__device__ __forceinline__ Log64Setup log64_setup(double x) {
+  Log64Setup S;
+  bool sub = x < 0x1p-1022;
+  double xs = sub ? x * 0x1p64 : x;
+  int hi = __double2hiint(xs);
+  S.j = (hi >> 16) & 15;
+  int fold = S.j >> 3;
+  S.e2 = ((hi >> 20) & 0x7ff) - 1023 + fold - (sub ? 64 : 0);
+  S.m = __hiloint2double((hi & 0x000fffff) | ((1023 - fold) << 20), __double2loint(xs));
+  return S;
+}
+
+// main-path error: below 2^-71 absolute with |y| >= 2^-5 (or a relative
+// 2^-104 when y = log1p t alone): the test uses 2^-65 |y|
+constexpr double LOG64_EPS = 0x1p-65;
+
+__device__ __forceinline__ double log64_fast(double x, const Log64Tab& tb, bool& ok) {
+  Log64Setup S = log64_setup(x);
+  double c = tb.c[S.j];
+  double4 L = tb.L[S.j];
+  dd p = two_prod(S.m, c);
+  dd t = fast_two_sum(p.hi - 1.0, p.lo);  // exact: p.hi - 1 is exact
+  // log1p t = t - t^2/2 + t^3/3 + t^4 S(t)
+  dd t2 = two_prod(t.hi, t.hi);
+  t2.lo = fma(2.0 * t.hi, t.lo, t2.lo);
+  dd t3 = dd_mul(t2, t);
+  dd b3 = dd_mul(t3, dd{THIRD_HI, THIRD_LO});
+  double sp = LOG64_S[LOG64_S_DEG];
+#pragma unroll
+  for (int i = LOG64_S_DEG - 1; i >= 0; i--) sp = fma(sp, t.hi, LOG64_S[i]);
+  double tail = t2.hi * t2.hi * sp;
+  dd l1 = dd_add(t, dd{-0.5 * t2.hi, -0.5 * t2.lo});
+  l1 = dd_add(l1, dd_add_d(b3, tail));
+  // e' ln2 - ln c_j
+  double ed = (double)S.e2;
+  dd el = dd_mul_d(dd{LN2_TD[0].x, LN2_TD[0].y}, ed);
+  dd y = dd_add(dd_add(el, dd{L.x, L.y}), l1);
+  double e = fabs(y.hi) * LOG64_EPS;
+  double a = y.hi + (y.lo - e);
+  double b = y.hi + (y.lo + e);
+  ok = a == b;
+  double res = b, spv;
+  if (log64_special(x, spv)) {
+    res = spv;
+    ok = true;
+  }
+  return res;
+}
+
+__device__ __noinline__ AccResultD log64_accurate(double x, const Log64Tab& tb) {
+  double sp;
+  if (log64_special(x, sp)) return {sp, 1};
+  Log64Setup S = log64_setup(x);
+  double c = tb.c[S.j];
+  dd p = two_prod(S.m, c);
+  dd t = fast_two_sum(p.hi - 1.0, p.lo);
+  td tt = td_from_dd(t);
+  // log1p t = 2 atanh(s), s = t/(2 + t), |s| < 1/32: series to s^29 (< 2^-145)
+  td s = td_div(tt, td_add(tt, td_from(2.0)));
+  td s2 = td_mul(s, s);
+  dd s2d = {s2.h, s2.m};
+  dd ph = {INV_ODD_DD[ATANH64_N].x, INV_ODD_DD[ATANH64_N].y};
+#pragma unroll
+  for (int k = ATANH64_N - 1; k >= 6; k--)
+    ph = dd_add(dd_mul(ph, s2d), dd{INV_ODD_DD[k].x, INV_ODD_DD[k].y});
+  td pt = td_from_dd(ph);
+#pragma unroll
+  for (int k = 5; k >= 0; k--) pt = td_add(td_mul(pt, s2), td_ld(INV_ODD_TD[k]));
+  td l = td_scale(td_mul(pt, s), 2.0);
+  td y = td_add(td_add(td_mul_d(td_ld(LN2_TD[0]), (double)S.e2), td_ld(tb.L[S.j])), l);
+  double e = fabs(y.h) * 0x1p-135;
+  bool ok;
+  double res = round64_tail(y.h, y.m, y.l, e, ok);
+  return {res, ok ? 1 : 0};
+}
+
+}  // namespace cr

@@ -10,7 +10,9 @@
 
 #include <stdlib.h>
 
+#include <algorithm>
 #include <atomic>
+#include <vector>
 #include <mutex>
 
 #include "../../include/cr.h"
@@ -20,6 +22,7 @@
 #include "cr_f32_trig.h"
 #include "cr_f32_atan.h"
 #include "cr_f32_hyp.h"
+#include "cr_f64.h"
 
 using namespace cr;
 
@@ -443,6 +446,431 @@ __global__ void __launch_bounds__(BLOCK)
   }
 }
 
+// ------------------------------------------------------------ binary64 map
+struct OpExp64 {
+  using Tab = Exp64Tab;
+  static __device__ __forceinline__ void load(Tab& t, int tid) { exp64_tab_load(t, tid); }
+  static __device__ __forceinline__ double fast(double x, const Tab& t, bool& ok) {
+    return exp64_fast(x, t, ok);
+  }
+  static __device__ __forceinline__ AccResultD accurate(double x, const Tab& t) {
+    return exp64_accurate(x, t);
+  }
+};
+struct OpLog64 {
+  using Tab = Log64Tab;
+  static __device__ __forceinline__ void load(Tab& t, int tid) { log64_tab_load(t, tid); }
+  static __device__ __forceinline__ double fast(double x, const Tab& t, bool& ok) {
+    return log64_fast(x, t, ok);
+  }
+  static __device__ __forceinline__ AccResultD accurate(double x, const Tab& t) {
+    return log64_accurate(x, t);
+  }
+};
+
+struct Deferred64 {
+  unsigned n, lanes, waves, esc;
+  unsigned idx[QCAP];
+  double x[QCAP];
+};
+
+template <class Op>
+__device__ __noinline__ void flush_queue64(Deferred64& q, const typename Op::Tab& tab, double* out,
+                                           DevStats* st, long long elem_base) {
+  unsigned n = q.n < QCAP ? q.n : QCAP;
+  for (unsigned k = threadIdx.x; k < n; k += BLOCK) {
+    AccResultD a = Op::accurate(q.x[k], tab);
+    out[q.idx[k]] = a.r;
+    if (!a.ok) {
+      atomicAdd(&q.esc, 1u);
+      note_escape(st, elem_base + q.idx[k]);
+    }
+  }
+  if (threadIdx.x == 0) {
+    q.lanes += n;
+    q.waves += (n + 63) / 64;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) q.n = 0;
+  __syncthreads();
+}
+
+// The binary64 form of k_map_f32: tiles of 2048 doubles, four 128-bit
+// double2 vectors per thread.
+constexpr int TILE64_U = 4;
+
+template <class Op>
+__global__ void __launch_bounds__(BLOCK)
+    k_map_f64(const double2* in, double2* out, long long n2, DevStats* st, unsigned flags,
+              long long elem_base) {
+  __shared__ typename Op::Tab tab;
+  __shared__ Deferred64 q;
+  Op::load(tab, threadIdx.x);
+  if (threadIdx.x == 0) {
+    q.n = 0;
+    q.lanes = q.waves = q.esc = 0;
+  }
+  __syncthreads();
+  const bool force = flags & CR_FLAG_FORCE_FALLBACK;
+  double* outd = reinterpret_cast<double*>(out);
+  const long long ntiles = (n2 + BLOCK * TILE64_U - 1) / (BLOCK * TILE64_U);
+  int iter = 0;
+  for (long long t = blockIdx.x; t < ntiles; t += gridDim.x, iter++) {
+    long long base = t * (BLOCK * TILE64_U) + threadIdx.x;
+    double2 v[TILE64_U];
+#pragma unroll
+    for (int u = 0; u < TILE64_U; u++) {
+      long long i = base + (long long)u * BLOCK;
+      if (i < n2) v[u] = in[i];
+    }
+#pragma unroll
+    for (int u = 0; u < TILE64_U; u++) {
+      long long i = base + (long long)u * BLOCK;
+      if (i < n2) {
+        double* e = reinterpret_cast<double*>(&v[u]);
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+          bool ok;
+          double x = e[c];
+          e[c] = Op::fast(x, tab, ok);
+          if (!ok || force) {
+            unsigned pos = atomicAdd(&q.n, 1u);
+            if (pos < QCAP) {
+              q.idx[pos] = (unsigned)(2 * i + c);
+              q.x[pos] = x;
+            } else {
+              AccResultD a = Op::accurate(x, tab);
+              e[c] = a.r;
+              atomicAdd(&q.lanes, 1u);
+              if (!a.ok) {
+                atomicAdd(&q.esc, 1u);
+                note_escape(st, elem_base + 2 * i + c);
+              }
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TILE64_U; u++) {
+      long long i = base + (long long)u * BLOCK;
+      if (i < n2) out[i] = v[u];
+    }
+    if (iter % QCHECK == QCHECK - 1) {
+      __syncthreads();
+      const unsigned nq = q.n;
+      __syncthreads();
+      if (nq > QFLUSH) flush_queue64<Op>(q, tab, outd, st, elem_base);
+    }
+  }
+  __syncthreads();
+  if (q.n) flush_queue64<Op>(q, tab, outd, st, elem_base);
+  if (threadIdx.x == 0 && q.lanes) {
+    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
+    atomicAdd(&c.fallback_lanes, (unsigned long long)q.lanes);
+    atomicAdd(&c.fallback_waves, (unsigned long long)q.waves);
+  }
+}
+
+template <class Op>
+__global__ void __launch_bounds__(BLOCK)
+    k_map_f64_scalar(const double* in, double* out, long long n, DevStats* st, unsigned flags,
+                     long long elem_base) {
+  __shared__ typename Op::Tab tab;
+  Op::load(tab, threadIdx.x);
+  __syncthreads();
+  const bool force = flags & CR_FLAG_FORCE_FALLBACK;
+  unsigned lanes = 0;
+  for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n;
+       i += (long long)gridDim.x * BLOCK) {
+    bool ok;
+    double x = in[i];
+    double r = Op::fast(x, tab, ok);
+    if (!ok || force) {
+      AccResultD a = Op::accurate(x, tab);
+      r = a.r;
+      lanes++;
+      if (!a.ok) note_escape(st, elem_base + i);
+    }
+    out[i] = r;
+  }
+  if (lanes) {
+    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
+    atomicAdd(&c.fallback_lanes, (unsigned long long)lanes);
+    atomicAdd(&c.fallback_waves, 1ull);
+  }
+}
+
+// ------------------------------------------------------------ ragged batch
+// One persistent kernel evaluates a whole plan: a request table (function,
+// pointers, length) and a tile table (request, start, count; tiles of 2048
+// elements).  Each workgroup walks a contiguous range of tiles; requests are
+// ordered by function when the plan is built, so consecutive tiles mostly
+// share a function and its LDS table, which is reloaded only when the
+// function changes.  The function switch is per tile, hence wave-uniform.
+struct BReq {
+  const void* in;
+  void* out;
+  long long n;
+  int func;
+  int aligned;  // in and out (and the cos block for sincosf) are 16-byte aligned
+};
+struct BTile {
+  int req;
+  int count;
+  long long start;
+};
+
+union BatchTab {
+  ExpTab e;
+  LogTab l;
+  TrigTab t;
+  AtanTab a;
+  NoTab z;
+};
+
+struct BDeferred {
+  unsigned n, lanes, waves, esc;
+  unsigned req[QCAP];
+  unsigned idx[QCAP];
+  float x[QCAP];
+};
+
+__device__ __forceinline__ void batch_tab_load(BatchTab& t, int func, int tid) {
+  switch (func) {
+    case CR_EXPF: case CR_EXP2F: case CR_EXP10F: case CR_EXPM1F:
+    case CR_SINHF: case CR_COSHF: case CR_TANHF:
+      exp_tab_load(t.e, tid);
+      break;
+    case CR_LOGF: case CR_LOG1PF: log_tab_load<LOGK_E>(t.l, tid); break;
+    case CR_LOG2F: log_tab_load<LOGK_2>(t.l, tid); break;
+    case CR_LOG10F: log_tab_load<LOGK_10>(t.l, tid); break;
+    case CR_SINF: case CR_COSF: case CR_SINCOSF: case CR_TANF: trig_tab_load(t.t, tid); break;
+    case CR_ASINF: case CR_ACOSF: case CR_ATANF: atan_tab_load(t.a, tid); break;
+    default: break;
+  }
+}
+
+template <class Op>
+__device__ __forceinline__ void batch_enqueue(BDeferred& q, const typename Op::Tab& tab,
+                                              unsigned req, unsigned idx, float x, float& res,
+                                              DevStats* st) {
+  unsigned pos = atomicAdd(&q.n, 1u);
+  if (pos < QCAP) {
+    q.req[pos] = req;
+    q.idx[pos] = idx;
+    q.x[pos] = x;
+  } else {
+    AccResult a = Op::accurate(x, tab);
+    res = a.r;
+    atomicAdd(&q.lanes, 1u);
+    if (!a.ok) {
+      atomicAdd(&q.esc, 1u);
+      note_escape(st, (long long)idx);
+    }
+  }
+}
+
+template <class Op>
+__device__ __noinline__ void batch_tile(BReq R, BTile T, const typename Op::Tab& tab,
+                                        BDeferred& q, bool force, DevStats* st) {
+  const float* in = reinterpret_cast<const float*>(R.in) + T.start;
+  float* out = reinterpret_cast<float*>(R.out) + T.start;
+  const int cnt = T.count;
+  const unsigned base = (unsigned)T.start;
+  if (R.aligned) {
+    const int n4 = cnt >> 2;
+#pragma unroll
+    for (int u = 0; u < TILE_U; u++) {
+      int i = threadIdx.x + u * BLOCK;
+      if (i < n4) {
+        float4 v = reinterpret_cast<const float4*>(in)[i];
+        float* e = reinterpret_cast<float*>(&v);
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+          bool ok;
+          float x = e[c];
+          e[c] = Op::fast(x, tab, ok);
+          if (!ok || force) batch_enqueue<Op>(q, tab, T.req, base + 4 * i + c, x, e[c], st);
+        }
+        reinterpret_cast<float4*>(out)[i] = v;
+      }
+    }
+    int i = 4 * n4 + threadIdx.x;
+    if (i < cnt) {
+      bool ok;
+      float x = in[i];
+      float r = Op::fast(x, tab, ok);
+      if (!ok || force) batch_enqueue<Op>(q, tab, T.req, base + i, x, r, st);
+      out[i] = r;
+    }
+  } else {
+    for (int i = threadIdx.x; i < cnt; i += BLOCK) {
+      bool ok;
+      float x = in[i];
+      float r = Op::fast(x, tab, ok);
+      if (!ok || force) batch_enqueue<Op>(q, tab, T.req, base + i, x, r, st);
+      out[i] = r;
+    }
+  }
+}
+
+__device__ __noinline__ void batch_tile_sincos(BReq R, BTile T, const TrigTab& tab,
+                                               BDeferred& q, bool force, DevStats* st) {
+  const float* in = reinterpret_cast<const float*>(R.in) + T.start;
+  float* os = reinterpret_cast<float*>(R.out) + T.start;
+  float* oc = reinterpret_cast<float*>(R.out) + R.n + T.start;
+  const int cnt = T.count;
+  const unsigned base = (unsigned)T.start;
+  for (int i = threadIdx.x; i < cnt; i += BLOCK) {
+    bool ok;
+    float x = in[i], c;
+    float sv = sincos_fast(x, tab, c, ok);
+    if (!ok || force) {
+      unsigned pos = atomicAdd(&q.n, 1u);
+      if (pos < QCAP) {
+        q.req[pos] = T.req;
+        q.idx[pos] = base + i;
+        q.x[pos] = x;
+      } else {
+        AccResult2 a = sincos_accurate(x, tab);
+        sv = a.s;
+        c = a.c;
+        atomicAdd(&q.lanes, 1u);
+        if (!a.ok) {
+          atomicAdd(&q.esc, 1u);
+          note_escape(st, (long long)(base + i));
+        }
+      }
+    }
+    os[i] = sv;
+    oc[i] = c;
+  }
+}
+
+template <class Op>
+__device__ __forceinline__ void batch_flush_op(BDeferred& q, unsigned n, const typename Op::Tab& tab,
+                                               const BReq* reqs, DevStats* st) {
+  for (unsigned k = threadIdx.x; k < n; k += BLOCK) {
+    AccResult a = Op::accurate(q.x[k], tab);
+    float* out = reinterpret_cast<float*>(reqs[q.req[k]].out);
+    out[q.idx[k]] = a.r;
+    if (!a.ok) {
+      atomicAdd(&q.esc, 1u);
+      note_escape(st, (long long)q.idx[k]);
+    }
+  }
+}
+
+// Run the accurate path on the queued elements (all of function func), then
+// empty the queue.  Called by all threads of the workgroup.
+__device__ __noinline__ void batch_flush(BDeferred& q, const BatchTab& tab, int func,
+                                         const BReq* reqs, DevStats* st) {
+  unsigned n = q.n < QCAP ? q.n : QCAP;
+  switch (func) {
+    case CR_EXPF: batch_flush_op<OpExp<EXPK_E>>(q, n, tab.e, reqs, st); break;
+    case CR_EXP2F: batch_flush_op<OpExp<EXPK_2>>(q, n, tab.e, reqs, st); break;
+    case CR_EXP10F: batch_flush_op<OpExp<EXPK_10>>(q, n, tab.e, reqs, st); break;
+    case CR_EXPM1F: batch_flush_op<OpExp<EXPK_EM1>>(q, n, tab.e, reqs, st); break;
+    case CR_LOGF: batch_flush_op<OpLog<LOGK_E>>(q, n, tab.l, reqs, st); break;
+    case CR_LOG2F: batch_flush_op<OpLog<LOGK_2>>(q, n, tab.l, reqs, st); break;
+    case CR_LOG10F: batch_flush_op<OpLog<LOGK_10>>(q, n, tab.l, reqs, st); break;
+    case CR_LOG1PF: batch_flush_op<OpLog<LOGK_1P>>(q, n, tab.l, reqs, st); break;
+    case CR_RSQRTF: batch_flush_op<OpRsqrt>(q, n, tab.z, reqs, st); break;
+    case CR_SINF: batch_flush_op<OpTrig<TRIGK_SIN>>(q, n, tab.t, reqs, st); break;
+    case CR_COSF: batch_flush_op<OpTrig<TRIGK_COS>>(q, n, tab.t, reqs, st); break;
+    case CR_TANF: batch_flush_op<OpTrig<TRIGK_TAN>>(q, n, tab.t, reqs, st); break;
+    case CR_SINCOSF:
+      for (unsigned k = threadIdx.x; k < n; k += BLOCK) {
+        AccResult2 a = sincos_accurate(q.x[k], tab.t);
+        const BReq& R = reqs[q.req[k]];
+        float* out = reinterpret_cast<float*>(R.out);
+        out[q.idx[k]] = a.s;
+        out[R.n + q.idx[k]] = a.c;
+        if (!a.ok) {
+          atomicAdd(&q.esc, 1u);
+          note_escape(st, (long long)q.idx[k]);
+        }
+      }
+      break;
+    case CR_ASINF: batch_flush_op<OpAtan<ATANK_ASIN>>(q, n, tab.a, reqs, st); break;
+    case CR_ACOSF: batch_flush_op<OpAtan<ATANK_ACOS>>(q, n, tab.a, reqs, st); break;
+    case CR_ATANF: batch_flush_op<OpAtan<ATANK_ATAN>>(q, n, tab.a, reqs, st); break;
+    case CR_SINHF: batch_flush_op<OpHyp<HYPK_SINH>>(q, n, tab.e, reqs, st); break;
+    case CR_COSHF: batch_flush_op<OpHyp<HYPK_COSH>>(q, n, tab.e, reqs, st); break;
+    case CR_TANHF: batch_flush_op<OpHyp<HYPK_TANH>>(q, n, tab.e, reqs, st); break;
+    default: break;
+  }
+  if (threadIdx.x == 0) {
+    q.lanes += n;
+    q.waves += (n + 63) / 64;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) q.n = 0;
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    k_batch(const BReq* reqs, const BTile* tiles, long long ntiles, DevStats* st,
+            unsigned flags) {
+  __shared__ BatchTab tab;
+  __shared__ BDeferred q;
+  if (threadIdx.x == 0) {
+    q.n = 0;
+    q.lanes = q.waves = q.esc = 0;
+  }
+  const bool force = flags & CR_FLAG_FORCE_FALLBACK;
+  // contiguous range of tiles for this workgroup
+  long long t0 = ntiles * blockIdx.x / gridDim.x, t1 = ntiles * (blockIdx.x + 1) / gridDim.x;
+  int cur = -1, iter = 0;
+  for (long long t = t0; t < t1; t++, iter++) {
+    const BTile T = tiles[t];
+    const BReq R = reqs[T.req];
+    if (R.func != cur) {
+      __syncthreads();
+      if (cur >= 0 && q.n) batch_flush(q, tab, cur, reqs, st);
+      batch_tab_load(tab, R.func, threadIdx.x);
+      cur = R.func;
+      __syncthreads();
+    }
+    switch (cur) {
+      case CR_EXPF: batch_tile<OpExp<EXPK_E>>(R, T, tab.e, q, force, st); break;
+      case CR_EXP2F: batch_tile<OpExp<EXPK_2>>(R, T, tab.e, q, force, st); break;
+      case CR_EXP10F: batch_tile<OpExp<EXPK_10>>(R, T, tab.e, q, force, st); break;
+      case CR_EXPM1F: batch_tile<OpExp<EXPK_EM1>>(R, T, tab.e, q, force, st); break;
+      case CR_LOGF: batch_tile<OpLog<LOGK_E>>(R, T, tab.l, q, force, st); break;
+      case CR_LOG2F: batch_tile<OpLog<LOGK_2>>(R, T, tab.l, q, force, st); break;
+      case CR_LOG10F: batch_tile<OpLog<LOGK_10>>(R, T, tab.l, q, force, st); break;
+      case CR_LOG1PF: batch_tile<OpLog<LOGK_1P>>(R, T, tab.l, q, force, st); break;
+      case CR_RSQRTF: batch_tile<OpRsqrt>(R, T, tab.z, q, force, st); break;
+      case CR_SINF: batch_tile<OpTrig<TRIGK_SIN>>(R, T, tab.t, q, force, st); break;
+      case CR_COSF: batch_tile<OpTrig<TRIGK_COS>>(R, T, tab.t, q, force, st); break;
+      case CR_SINCOSF: batch_tile_sincos(R, T, tab.t, q, force, st); break;
+      case CR_TANF: batch_tile<OpTrig<TRIGK_TAN>>(R, T, tab.t, q, force, st); break;
+      case CR_ASINF: batch_tile<OpAtan<ATANK_ASIN>>(R, T, tab.a, q, force, st); break;
+      case CR_ACOSF: batch_tile<OpAtan<ATANK_ACOS>>(R, T, tab.a, q, force, st); break;
+      case CR_ATANF: batch_tile<OpAtan<ATANK_ATAN>>(R, T, tab.a, q, force, st); break;
+      case CR_SINHF: batch_tile<OpHyp<HYPK_SINH>>(R, T, tab.e, q, force, st); break;
+      case CR_COSHF: batch_tile<OpHyp<HYPK_COSH>>(R, T, tab.e, q, force, st); break;
+      case CR_TANHF: batch_tile<OpHyp<HYPK_TANH>>(R, T, tab.e, q, force, st); break;
+      default: break;
+    }
+    if (iter % QCHECK == QCHECK - 1) {
+      __syncthreads();
+      const unsigned nq = q.n;
+      __syncthreads();
+      if (nq > QFLUSH) batch_flush(q, tab, cur, reqs, st);
+    }
+  }
+  __syncthreads();
+  if (cur >= 0 && q.n) batch_flush(q, tab, cur, reqs, st);
+  if (threadIdx.x == 0 && q.lanes) {
+    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
+    atomicAdd(&c.fallback_lanes, (unsigned long long)q.lanes);
+    atomicAdd(&c.fallback_waves, (unsigned long long)q.waves);
+  }
+}
+
 __global__ void k_zero_stats(DevStats* st) {
   unsigned long long* p = reinterpret_cast<unsigned long long*>(st);
   for (int i = threadIdx.x; i < (int)(sizeof(DevStats) / 8); i += blockDim.x) p[i] = 0;
@@ -573,8 +1001,49 @@ int launch_sincos(const float* in, float* out, size_t n, hipStream_t s, unsigned
   return CR_OK;
 }
 
+template <class Op>
+int launch_map_f64(const double* in, double* out, size_t n, hipStream_t s, unsigned flags,
+                   DevStats* st) {
+  uintptr_t ai = (uintptr_t)in, ao = (uintptr_t)out;
+  size_t head = 0;
+  if ((ai & 15) == (ao & 15)) {
+    head = ((16 - (ai & 15)) & 15) / 8;
+    if (head > n) head = n;
+  } else {
+    head = n;
+  }
+  size_t body2 = (n - head) / 2;
+  size_t tail = n - head - 2 * body2;
+  if (head) {
+    hipLaunchKernelGGL(k_map_f64_scalar<Op>, dim3((unsigned)((head + BLOCK - 1) / BLOCK > 65536
+                                                               ? 65536
+                                                               : (head + BLOCK - 1) / BLOCK)),
+                       dim3(BLOCK), 0, s, in, out, (long long)head, st, flags, 0LL);
+  }
+  for (size_t done = 0; done < body2;) {
+    size_t chunk2 = body2 - done;
+    if (chunk2 > ((size_t)1 << 30)) chunk2 = (size_t)1 << 30;
+    size_t tiles = (chunk2 + BLOCK * TILE64_U - 1) / (BLOCK * TILE64_U);
+    size_t g = tiles < (size_t)grid_blocks() ? tiles : (size_t)grid_blocks();
+    size_t off = head + 2 * done;
+    hipLaunchKernelGGL(k_map_f64<Op>, dim3((unsigned)g), dim3(BLOCK), 0, s,
+                       reinterpret_cast<const double2*>(in + off),
+                       reinterpret_cast<double2*>(out + off), (long long)chunk2, st, flags,
+                       (long long)off);
+    done += chunk2;
+  }
+  if (tail) {
+    size_t off = head + 2 * body2;
+    hipLaunchKernelGGL(k_map_f64_scalar<Op>, dim3(1), dim3(BLOCK), 0, s, in + off, out + off,
+                       (long long)tail, st, flags, (long long)off);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e);
+  return CR_OK;
+}
+
 bool func_valid(int f) { return (f >= 0 && f < CR_NUM_F32) || f == CR_EXP || f == CR_LOG; }
-bool func_built(int f) { return f >= CR_EXPF && f <= CR_TANHF; }
+bool func_built(int f) { return (f >= CR_EXPF && f <= CR_TANHF) || f == CR_EXP || f == CR_LOG; }
 
 int dispatch_f32(int f, const float* in, float* out, size_t n, hipStream_t s, unsigned flags,
                  DevStats* st) {
@@ -602,6 +1071,82 @@ int dispatch_f32(int f, const float* in, float* out, size_t n, hipStream_t s, un
   return CR_E_FUNC;
 }
 
+
+// ------------------------------------------------------------ batch plans
+}  // namespace
+
+struct cr_batch_plan {
+  int device;
+  BReq* d_reqs;
+  BTile* d_tiles;
+  long long ntiles;
+  int grid;
+  unsigned flags;
+  hipGraphExec_t exec;
+  hipEvent_t done;
+  bool launched;
+  long long elems;
+};
+
+namespace {
+
+// Validate requests and build the request and tile tables (host side).
+int build_tables(const cr_request* reqs, int32_t num, std::vector<BReq>& hr,
+                 std::vector<BTile>& ht, long long& elems) {
+  if (num < 0) return CR_E_SIZE;
+  if (num > 0 && !reqs) return CR_E_NULL;
+  hr.clear();
+  ht.clear();
+  elems = 0;
+  std::vector<int> order(num);
+  for (int i = 0; i < num; i++) {
+    const cr_request& r = reqs[i];
+    if (r.func_id < 0 || r.func_id >= CR_NUM_F32) return CR_E_FUNC;
+    if (r.impl != CR_IMPL_AUTO && r.impl != CR_IMPL_F64_INTERNAL) return CR_E_IMPL;
+    if (r.n < 0 || r.n >= ((int64_t)1 << 31)) return CR_E_SIZE;
+    if (r.n == 0) continue;
+    if (!r.in || !r.out) return CR_E_NULL;
+    uintptr_t a = (uintptr_t)r.in, b = (uintptr_t)r.out;
+    if ((a & 3) || (b & 3)) return CR_E_ALIGN;
+    size_t nout = r.func_id == CR_SINCOSF ? 2 * (size_t)r.n : (size_t)r.n;
+    bool same = a == b && nout == (size_t)r.n;
+    if (!same && a < b + nout * 4 && b < a + (size_t)r.n * 4) return CR_E_OVERLAP;
+    if (!cr_available(r.func_id, r.impl)) return CR_E_IMPL;
+  }
+  // order requests by function so that tiles of one function are adjacent
+  for (int i = 0; i < num; i++) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return reqs[x].func_id < reqs[y].func_id; });
+  for (int oi = 0; oi < num; oi++) {
+    const cr_request& r = reqs[order[oi]];
+    if (r.n == 0) continue;
+    BReq q;
+    q.in = r.in;
+    q.out = r.out;
+    q.n = r.n;
+    q.func = r.func_id;
+    uintptr_t a = (uintptr_t)r.in, b = (uintptr_t)r.out;
+    uintptr_t c = b + 4 * (uintptr_t)r.n;
+    q.aligned = ((a | b) & 15) == 0 && (r.func_id != CR_SINCOSF || (c & 15) == 0);
+    int ri = (int)hr.size();
+    hr.push_back(q);
+    for (long long s = 0; s < r.n; s += TILE) {
+      BTile t;
+      t.req = ri;
+      t.start = s;
+      t.count = (int)((r.n - s) < TILE ? (r.n - s) : TILE);
+      ht.push_back(t);
+    }
+    elems += r.n;
+  }
+  return CR_OK;
+}
+
+}  // namespace
+
+extern "C" int cr_batch_plan_destroy(cr_batch_plan* plan);
+
+namespace {
 }  // namespace
 
 extern "C" {
@@ -629,8 +1174,10 @@ int cr_eval_ex(int func_id, int impl, unsigned flags, const void* in, void* out,
   hipStream_t s = (hipStream_t)stream;
   if (func_id < CR_NUM_F32)
     rc = dispatch_f32(func_id, (const float*)in, (float*)out, n, s, flags, st);
+  else if (func_id == CR_EXP)
+    rc = launch_map_f64<OpExp64>((const double*)in, (double*)out, n, s, flags, st);
   else
-    rc = CR_E_IMPL;
+    rc = launch_map_f64<OpLog64>((const double*)in, (double*)out, n, s, flags, st);
   if (rc == CR_OK) {
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -647,6 +1194,127 @@ int cr_available(int func_id, int impl) {
 
 int cr_eval(int func_id, const void* in, void* out, size_t n, void* stream) {
   return cr_eval_ex(func_id, CR_IMPL_AUTO, 0u, in, out, n, stream);
+}
+
+
+int cr_batch_plan_create(const cr_request* reqs, int32_t num, unsigned flags,
+                         cr_batch_plan** plan) {
+  if (!plan) return CR_E_NULL;
+  *plan = nullptr;
+  std::vector<BReq> hr;
+  std::vector<BTile> ht;
+  long long elems = 0;
+  int rc = build_tables(reqs, num, hr, ht, elems);
+  if (rc) return rc;
+  DevStats* st = nullptr;
+  rc = get_stats(&st);
+  if (rc) return rc;
+  cr_batch_plan* p = new cr_batch_plan();
+  (void)hipGetDevice(&p->device);
+  p->flags = flags;
+  p->ntiles = (long long)ht.size();
+  p->elems = elems;
+  p->grid = (int)(p->ntiles < grid_blocks() ? p->ntiles : grid_blocks());
+  hipError_t e = hipSuccess;
+  if (!hr.empty()) e = hipMalloc(&p->d_reqs, hr.size() * sizeof(BReq));
+  if (e == hipSuccess && !ht.empty()) e = hipMalloc(&p->d_tiles, ht.size() * sizeof(BTile));
+  if (e != hipSuccess) {
+    t_last_hip = (int)e;
+    cr_batch_plan_destroy(p);
+    return CR_E_NOMEM;
+  }
+  if (!hr.empty()) e = hipMemcpy(p->d_reqs, hr.data(), hr.size() * sizeof(BReq), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !ht.empty())
+    e = hipMemcpy(p->d_tiles, ht.data(), ht.size() * sizeof(BTile), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+  // capture the single launch in a graph (a private stream at default priority)
+  if (e == hipSuccess && p->grid > 0) {
+    hipStream_t cs = nullptr;
+    hipGraph_t g = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_batch, dim3(p->grid), dim3(BLOCK), 0, cs, p->d_reqs, p->d_tiles,
+                         p->ntiles, st, flags);
+      hipError_t e2 = hipStreamEndCapture(cs, &g);
+      e = hipGetLastError();
+      if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+  if (e != hipSuccess) {
+    t_last_hip = (int)e;
+    cr_batch_plan_destroy(p);
+    return CR_E_HIP;
+  }
+  *plan = p;
+  return CR_OK;
+}
+
+int cr_batch_plan_launch(cr_batch_plan* plan, void* stream) {
+  if (!plan) return CR_E_NULL;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->exec) {
+    hipError_t e = hipGraphLaunch(plan->exec, s);
+    if (e == hipSuccess) e = hipEventRecord(plan->done, s);
+    if (e != hipSuccess) return hip_fail(e);
+    plan->launched = true;
+    g_elems[plan->device] += plan->elems;
+  }
+  return CR_OK;
+}
+
+int cr_batch_plan_destroy(cr_batch_plan* plan) {
+  if (!plan) return CR_OK;
+  if (plan->launched && plan->done) (void)hipEventSynchronize(plan->done);
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->done) (void)hipEventDestroy(plan->done);
+  if (plan->d_reqs) (void)hipFree(plan->d_reqs);
+  if (plan->d_tiles) (void)hipFree(plan->d_tiles);
+  delete plan;
+  return CR_OK;
+}
+
+int cr_eval_batch(const cr_request* reqs, int32_t num, void* stream) {
+  std::vector<BReq> hr;
+  std::vector<BTile> ht;
+  long long elems = 0;
+  int rc = build_tables(reqs, num, hr, ht, elems);
+  if (rc) return rc;
+  if (ht.empty()) return CR_OK;
+  DevStats* st = nullptr;
+  rc = get_stats(&st);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  BReq* dr = nullptr;
+  BTile* dt = nullptr;
+  hipError_t e = hipMallocAsync((void**)&dr, hr.size() * sizeof(BReq), s);
+  if (e == hipSuccess) e = hipMallocAsync((void**)&dt, ht.size() * sizeof(BTile), s);
+  if (e != hipSuccess) {
+    if (dr) (void)hipFreeAsync(dr, s);
+    t_last_hip = (int)e;
+    return CR_E_NOMEM;
+  }
+  e = hipMemcpyAsync(dr, hr.data(), hr.size() * sizeof(BReq), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dt, ht.data(), ht.size() * sizeof(BTile), hipMemcpyHostToDevice, s);
+  // the host vectors are freed on return: make sure the copies have read them
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) {
+    long long nt = (long long)ht.size();
+    int g = (int)(nt < grid_blocks() ? nt : grid_blocks());
+    hipLaunchKernelGGL(k_batch, dim3(g), dim3(BLOCK), 0, s, dr, dt, nt, st, 0u);
+    e = hipGetLastError();
+  }
+  (void)hipFreeAsync(dt, s);
+  (void)hipFreeAsync(dr, s);
+  if (e != hipSuccess) return hip_fail(e);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  g_elems[dev] += elems;
+  return CR_OK;
 }
 
 int cr_stats_reset(void* stream) {

@@ -62,29 +62,36 @@ def cheb_nodes(a, b, n):
 
 
 def lawson_fit(g, w, a, b, powers, npts=500, iters=40):
-    """Coefficients c_k (mp) minimising max |w(x) (g(x) - sum c_k x^p_k)| on [a,b]."""
-    xs = cheb_nodes(a, b, npts) + [mp.mpf(a), mp.mpf(b)]
-    gs = [g(x) for x in xs]
-    ws = [w(x) for x in xs]
-    W = [mp.mpf(1)] * len(xs)
-    m = len(powers)
-    c = None
-    for _ in range(iters):
-        A = mp.matrix(m, m)
-        B = mp.matrix(m, 1)
-        for x, gx, wx, Wi in zip(xs, gs, ws, W):
-            s = Wi * wx * wx
-            pw = [x ** p for p in powers]
-            for k in range(m):
-                B[k] += s * gx * pw[k]
-                for l in range(m):
-                    A[k, l] += s * pw[k] * pw[l]
-        c = mp.lu_solve(A, B)
-        errs = [abs(wx * (gx - sum(c[k] * x ** powers[k] for k in range(m))))
-                for x, gx, wx in zip(xs, gs, ws)]
-        tot = sum(Wi * e for Wi, e in zip(W, errs))
-        W = [Wi * e / tot for Wi, e in zip(W, errs)]
-    return [c[k] for k in range(m)]
+    """Coefficients c_k (mp) minimising max |w(x) (g(x) - sum c_k x^p_k)| on [a,b].
+    The fit runs in the scaled variable u = x / max(|a|, |b|) (bounded powers,
+    well-conditioned normal equations) at 400 bits."""
+    with mp.workprec(400):
+        sc = max(abs(mp.mpf(a)), abs(mp.mpf(b)))
+        xs = cheb_nodes(a, b, npts) + [mp.mpf(a), mp.mpf(b)]
+        gs = [g(x) for x in xs]
+        ws = [w(x) for x in xs]
+        wmax = max(abs(v) for v in ws)
+        ws = [v / wmax for v in ws]
+        us = [x / sc for x in xs]
+        W = [mp.mpf(1)] * len(xs)
+        m = len(powers)
+        c = None
+        for _ in range(iters):
+            A = mp.matrix(m, m)
+            B = mp.matrix(m, 1)
+            for u, gx, wx, Wi in zip(us, gs, ws, W):
+                s2 = Wi * wx * wx
+                pw = [u ** p for p in powers]
+                for k in range(m):
+                    B[k] += s2 * gx * pw[k]
+                    for l in range(m):
+                        A[k, l] += s2 * pw[k] * pw[l]
+            c = mp.lu_solve(A, B)
+            errs = [abs(wx * (gx - sum(c[k] * u ** powers[k] for k in range(m))))
+                    for u, gx, wx in zip(us, gs, ws)]
+            tot = sum(Wi * e for Wi, e in zip(W, errs))
+            W = [Wi * e / tot for Wi, e in zip(W, errs)]
+        return [c[k] / sc ** powers[k] for k in range(m)]
 
 
 def max_err(fn, a, b, n=4000):
@@ -112,6 +119,15 @@ def emit_dd_table(name, vals, comment):
     for v in vals:
         hi, lo = dd(v)
         emit("  {%s, %s}," % (hexd(hi), hexd(lo)))
+    emit("};")
+
+
+def emit_td_table(name, vals, comment):
+    emit("// " + comment)
+    emit("__device__ __constant__ const double4 %s[%d] = {" % (name, len(vals)))
+    for v in vals:
+        a, b, c = td(mp.mpf(v))
+        emit("  {%s, %s, %s, 0.0}," % (hexd(a), hexd(b), hexd(c)))
     emit("};")
 
 
@@ -364,6 +380,74 @@ def gen_atan():
     emit()
 
 
+# ============================================================ binary64 exp / log
+def gen_f64():
+    emit("// ---- binary64 exp and log ----")
+    with mp.workprec(600):
+        ln2 = mp.log(2)
+        emit_td_table("EXP64_T1", [mp.power(2, mp.mpf(i) / 16) for i in range(16)],
+                      "2^(i/16) as triple-double {hi, mid, lo, 0}")
+        emit_td_table("EXP64_T2", [mp.power(2, mp.mpf(i) / 256) for i in range(16)],
+                      "2^(i/256) as triple-double {hi, mid, lo, 0}")
+        # ln2/256 in four parts; C1 on 34 bits: k C1 exact for |k| < 2^19
+        c = ln2 / 256
+        c1 = split_bits(c, 34)
+        r = c - mp.mpf(c1)
+        c2 = float(r)
+        r -= mp.mpf(c2)
+        c3 = float(r)
+        r -= mp.mpf(c3)
+        c4 = float(r)
+        emit_const("EXP64_C1", c1, "ln2/256 rounded to 34 bits")
+        emit_const("EXP64_C2", c2)
+        emit_const("EXP64_C3", c3)
+        emit_const("EXP64_C4", c4)
+        emit_const("EXP64_INV", d(256 / ln2), "256/ln2")
+        emit_td_table("INV_FACT_TD", [1 / mp.factorial(k) for k in range(8)],
+                      "1/k! as triple-double, k = 0..7")
+        emit_td_table("LN2_TD", [ln2], "ln 2 as triple-double")
+        iv = log_intervals()
+        emit_td_table("LOG64_L", [-mp.log(c) for _, _, c in iv], "-ln(c_j) as triple-double")
+        emit_td_table("INV_ODD_TD", [mp.mpf(1) / (2 * k + 1) for k in range(8)],
+                      "1/(2k+1) as triple-double, k = 0..7")
+        h, l = dd(mp.mpf(1) / 3)
+        emit_const("THIRD_HI", h)
+        emit_const("THIRD_LO", l)
+    # fast exp: e^r - 1 - r = r^2 P(r), |r| <= rho
+    rho = mp.log(2) / 512 * mp.mpf("1.0001")
+    for deg in range(3, 8):
+        cs = lawson_fit(lambda r: (mp.expm1(r) - r) / (r * r) if r != 0 else mp.mpf(0.5),
+                        lambda r: r * r, -rho, rho, list(range(deg + 1)), npts=120, iters=16)
+        cd = [d(v) for v in cs]
+        err = max_err(lambda r: mp.expm1(r) - r - r * r * sum(mp.mpf(cd[k]) * r ** k
+                                                              for k in range(len(cd))), -rho, rho)
+        if err < mp.mpf(2) ** -80:
+            break
+    emit("// e^r - 1 = r + r^2 P(r), |r| <= ln2/512; |error| <= 2^%.2f (absolute)"
+         % log2_of(err * mp.mpf("1.25")))
+    emit_arr("EXP64_P", cd, "coefficients (degree %d)" % (len(cd) - 1))
+    emit("#define EXP64_P_DEG %d" % (len(cd) - 1))
+    # fast log: log1p(t) = t - t^2/2 + t^3/3 + t^4 S(t), t in [-1/32, 1/16]
+    iv = log_intervals()
+    a = min(lo * c - 1 for lo, hi, c in iv) * mp.mpf("1.0001")
+    b = max(hi * c - 1 for lo, hi, c in iv) * mp.mpf("1.0001")
+    g = lambda t: (mp.log1p(t) - t + t * t / 2 - t ** 3 / 3) / t ** 4 if t != 0 else mp.mpf(-1) / 4
+    for deg in range(9, 18):
+        cs = lawson_fit(g, lambda t: t ** 4, a, b, list(range(deg + 1)), npts=160, iters=14)
+        cd = [d(v) for v in cs]
+        err = max_err(lambda t: mp.log1p(t) - t + t * t / 2 - t ** 3 / 3
+                      - t ** 4 * sum(mp.mpf(cd[k]) * t ** k for k in range(len(cd))), a, b)
+        if err < mp.mpf(2) ** -78:
+            break
+    emit("// log1p t = t - t^2/2 + t^3/3 + t^4 S(t), t in [%s, %s]; |error| <= 2^%.2f (absolute)"
+         % (mp.nstr(a, 6), mp.nstr(b, 6), log2_of(err * mp.mpf("1.25"))))
+    emit_arr("LOG64_S", cd, "coefficients (degree %d)" % (len(cd) - 1))
+    emit("#define LOG64_S_DEG %d" % (len(cd) - 1))
+    emit("#define ATANH64_N 16")
+    emit_dd_table("INV_ODD_DD", [mp.mpf(1) / (2 * k + 1) for k in range(17)], "1/(2k+1), k = 0..16")
+    emit()
+
+
 def main():
     emit("// Generated by paper_2605_15547_amd/gen/gen_consts.py -- do not edit.")
     emit("// Tables and polynomial coefficients of the correctly rounded kernels.")
@@ -374,6 +458,7 @@ def main():
     gen_log()
     gen_trig()
     gen_atan()
+    gen_f64()
     with open(OUT, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("wrote", OUT)

@@ -62,3 +62,28 @@ def test_argument_validation(L):
     assert ev(0, 7, 0, vp(0x1000), vp(0x2000), 8, None) == -5
     assert L.cr_available(0, 7) == 0
     assert L.cr_available(99, 0) == 0
+
+
+def test_batch_validation(L):
+    """Batch requests are validated on the host before anything touches a GPU."""
+    from paper_2605_15547_amd import crmath as C
+    vp = ctypes.c_void_p
+    plan = vp()
+
+    def create(reqs):
+        arr = C._requests(reqs)
+        return L.cr_batch_plan_create(arr, len(reqs), 0, ctypes.byref(plan))
+
+    assert L.cr_batch_plan_create(None, 1, 0, ctypes.byref(plan)) == -2
+    assert create([("expf", 0x1000, 0x2000, 8), (64, 0x3000, 0x4000, 8)]) == -1  # binary64
+    assert create([(19, 0x1000, 0x2000, 8)]) == -1
+    assert create([("expf", 0x1000, 0x2000, -1)]) == -9
+    assert create([("expf", 0x1000, 0x2000, 1 << 31)]) == -9
+    assert create([("expf", 0, 0x2000, 8)]) == -2
+    assert create([("expf", 0x1002, 0x2000, 8)]) == -4
+    assert create([("logf", 0x1000, 0x1008, 8)]) == -3
+    assert create([("sincosf", 0x1000, 0x1000, 8)]) == -3
+    assert create([("expf", 0x1000, 0x2000, 8, 9)]) == -5
+    assert plan.value is None
+    assert L.cr_batch_plan_launch(None, None) == -2
+    assert L.cr_batch_plan_destroy(None) == 0
