@@ -13,6 +13,11 @@ algorithmic bytes (4 B in + 4 B out per element) over its average launch
 time, measured with HIP events on the stream it runs on.  cpu_baseline times
 the CPU oracle (oracle/) on a bounded sample of the same inputs.
 
+other_workloads (left out with --headline-only) reports, outside the headline
+value: the trig/inverse-trig/hyperbolic family at the same size, binary64
+exp/log on 2^24 inputs each, and the ragged batch of 4096 mixed requests
+evaluated by one graph launch per step (plan creation timed separately).
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n LOG2N]
 """
 import argparse
@@ -28,6 +33,84 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FAMILY = ["expf", "exp2f", "exp10f", "expm1f", "logf", "log2f", "log10f", "log1pf", "rsqrtf"]
+TRIG = ["sinf", "cosf", "sincosf", "tanf", "asinf", "acosf", "atanf", "sinhf", "coshf", "tanhf"]
+
+
+def bytes_per_elem(func):
+    return 16 if func in ("exp", "log") else (12 if func == "sincosf" else 8)
+
+
+def bench_family(torch, crmath, inputs, funcs, n, impl, steps, warmup, stream):
+    """Gelem/s and HBM fraction per function (inputs resident in HBM), plus the
+    accurate-path share, for a family workload of n elements per function."""
+    sp = crmath._stream_ptr(stream)
+    res = {}
+    for f in funcs:
+        if not crmath.available(f, impl):
+            res[f] = None
+            continue
+        x = inputs.workload_f64(f, n) if f in ("exp", "log") else inputs.workload_f32(f, n)
+        xt = torch.from_numpy(x).cuda()
+        ot = torch.empty(2 * n if f == "sincosf" else n, dtype=xt.dtype, device="cuda")
+        for _ in range(warmup):
+            crmath.eval_ptr(f, xt.data_ptr(), ot.data_ptr(), n, impl, 0, sp)
+        torch.cuda.synchronize()
+        crmath.stats_reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            crmath.eval_ptr(f, xt.data_ptr(), ot.data_ptr(), n, impl, 0, sp)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        st = crmath.stats_read()
+        ms = e0.elapsed_time(e1) / steps
+        gbs = bytes_per_elem(f) * n / (ms * 1e-3) / 1e9
+        res[f] = {"ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                  "gb_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                  "fallback_lane_rate": st["fallback_lanes"] / (n * steps),
+                  "escapes": st["escapes"]}
+        del xt, ot
+    log("bench: family", funcs[0], "...", {k: v and v["gelem_s"] for k, v in res.items()})
+    return {"elems_per_function": n, "per_func": res}
+
+
+def bench_batch(torch, crmath, inputs, steps, warmup, stream):
+    """The ragged batch: 4096 requests of mixed binary32 functions, lengths
+    log-uniform in [1, 2^20], evaluated by one graph launch per step."""
+    funcs, lens, seeds = inputs.batch_requests()
+    bufs, reqs = [], []
+    total, nbytes = 0, 0
+    for f, n, sd in zip(funcs, lens, seeds):
+        n = int(n)
+        x = inputs.workload_f32(f, n, seed=int(sd))
+        xt = torch.from_numpy(x).cuda()
+        ot = torch.empty(2 * n if f == "sincosf" else n, dtype=torch.float32, device="cuda")
+        bufs.append((xt, ot))
+        reqs.append((f, xt.data_ptr(), ot.data_ptr(), n))
+        total += n
+        nbytes += bytes_per_elem(f) * n
+    t0 = time.perf_counter()
+    plan = crmath.BatchPlan(reqs)
+    create_s = time.perf_counter() - t0
+    for _ in range(warmup):
+        plan.launch(stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan.launch(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    plan.destroy()
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    r = {"requests": len(reqs), "elements": total, "ms": round(ms, 3),
+         "gelem_s": round(total / (ms * 1e-3) / 1e9, 2), "gb_s": round(gbs, 1),
+         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "plan_create_s": round(create_s, 3)}
+    log("bench: batch", r)
+    del bufs
+    torch.cuda.empty_cache()
+    return r
 
 
 def log(*a):
@@ -67,6 +150,8 @@ def main():
     ap.add_argument("--impl", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="measure only the exp/log-family step (profiling runs)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also time a plain copy of one input (profiler calibration)")
     a = ap.parse_args()
@@ -150,6 +235,18 @@ def main():
         torch.cuda.synchronize()
         copy_ms = e0.elapsed_time(e1) / a.steps
 
+    extra = {}
+    if not a.headline_only:
+        # free the headline buffers, then measure the other workloads
+        del xs, outs
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        extra["trig_hyperbolic_family"] = bench_family(
+            torch, crmath, inputs, TRIG, n, a.impl, a.steps, a.warmup, stream)
+        extra["binary64_exp_log"] = bench_family(
+            torch, crmath, inputs, ["exp", "log"], 1 << 24, 0, a.steps, a.warmup, stream)
+        extra["ragged_batch"] = bench_batch(torch, crmath, inputs, a.steps, a.warmup, stream)
+
     cpu = None
     if not a.no_cpu_baseline:
         # the oracle as it is, on a bounded sample: consecutive 2^14-element
@@ -183,7 +280,7 @@ def main():
            "fallback": {"lanes": st["fallback_lanes"], "waves": st["fallback_waves"],
                         "escapes": st["escapes"],
                         "lane_rate": st["fallback_lanes"] / max(1, total_elems)},
-           "roofline": roof, "cpu_baseline": cpu}
+           "roofline": roof, "cpu_baseline": cpu, "other_workloads": extra}
     if copy_ms is not None:
         rec["copy_ref"] = {"ms": round(copy_ms, 4), "bytes": 8 * n,
                            "gb_s": round(8 * n / (copy_ms * 1e-3) / 1e9, 1)}
