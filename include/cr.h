@@ -58,7 +58,10 @@ enum cr_func {
 enum cr_impl {
   CR_IMPL_AUTO = 0,         /* library default (currently F64_INTERNAL) */
   CR_IMPL_F64_INTERNAL = 1, /* binary64 fast path + double-double accurate path */
-  CR_IMPL_SPLIT_F32 = 2     /* binary32-only double-float path (not yet built: CR_E_IMPL) */
+  CR_IMPL_SPLIT_F32 = 2     /* binary32-only float-float fast path; lanes that fail its
+                             * rounding test take the binary64 accurate path.  Built for
+                             * the functions where cr_available(f, CR_IMPL_SPLIT_F32)
+                             * is 1; the others give CR_E_IMPL */
 };
 
 enum cr_flag {

@@ -1,0 +1,172 @@
+"""Generates paper_2605_15547_amd/csrc/cr_split_consts.h: the tables and
+constants of the binary32-only ("split", float-float) kernels.
+
+Every value is computed with mpmath at high precision and rounded directly to
+binary32 (never through binary64, which would round twice); a float-float
+entry is the pair hi = RN32(v), lo = RN32(v - hi).  Run:
+    python paper_2605_15547_amd/gen/gen_split_consts.py
+"""
+import os
+
+import mpmath as mp
+
+mp.mp.prec = 300
+HERE = os.path.dirname(os.path.abspath(__file__))
+OUT = os.path.join(os.path.dirname(HERE), "csrc", "cr_split_consts.h")
+
+
+def f32(x, mode="n"):
+    """x rounded to binary32 (normal range): mode n = nearest-even, z = toward 0"""
+    x = mp.mpf(x)
+    if x == 0:
+        return 0.0
+    e = int(mp.floor(mp.log(abs(x), 2)))
+    q = mp.mpf(2) ** (e - 23)
+    while abs(x) / q >= 2 ** 24:
+        q *= 2
+    while abs(x) / q < 2 ** 23:
+        q /= 2
+    t = x / q
+    n = mp.nint(t) if mode == "n" else (mp.floor(t) if t > 0 else mp.ceil(t))
+    if mode == "n" and abs(t - mp.floor(t) - mp.mpf(0.5)) == 0:  # tie: even
+        n = mp.floor(t) if int(mp.floor(t)) % 2 == 0 else mp.ceil(t)
+    v = n * q
+    return float(v)  # exact: v has 24 bits
+
+
+def bits(x, nb, mode="z"):
+    """x rounded to nb significant bits (toward zero by default)"""
+    x = mp.mpf(x)
+    e = int(mp.floor(mp.log(abs(x), 2)))
+    q = mp.mpf(2) ** (e - nb + 1)
+    t = x / q
+    n = (mp.floor(t) if t > 0 else mp.ceil(t)) if mode == "z" else mp.nint(t)
+    return float(n * q)
+
+
+def ff(x):
+    x = mp.mpf(x)
+    hi = f32(x)
+    lo = f32(x - mp.mpf(hi)) if x != mp.mpf(hi) else 0.0
+    return hi, lo
+
+
+def fx(v):
+    v = float(v)
+    if v == 0.0:
+        return "0.0f"
+    return v.hex() + "f"
+
+
+lines = []
+
+
+def emit(s=""):
+    lines.append(s)
+
+
+def emit_ff_table(name, vals, comment):
+    emit("// " + comment)
+    emit("__device__ __constant__ const float2 %s[%d] = {" % (name, len(vals)))
+    for v in vals:
+        hi, lo = ff(v)
+        emit("  {%s, %s}," % (fx(hi), fx(lo)))
+    emit("};")
+
+
+def emit_f(name, v, comment=""):
+    emit("#define %s (%s)%s" % (name, fx(v), ("  /* " + comment + " */") if comment else ""))
+
+
+def gen_exp():
+    emit("// ---- exponential family, binary32-only ----")
+    emit_ff_table("SEXP_T1", [mp.power(2, mp.mpf(j) / 16) for j in range(-8, 8)],
+                  "2^(j/16), j = -8..7 (index j + 8), float-float")
+    emit_ff_table("SEXP_T2", [mp.power(2, mp.mpf(j) / 256) for j in range(-8, 8)],
+                  "2^(j/256), j = -8..7 (index j + 8), float-float")
+    emit_ff_table("SEXP_D1", [mp.power(2, mp.mpf(j) / 16) - 1 for j in range(-8, 8)],
+                  "2^(j/16) - 1, j = -8..7, float-float")
+    emit_ff_table("SEXP_D2", [mp.power(2, mp.mpf(j) / 256) - 1 for j in range(-8, 8)],
+                  "2^(j/256) - 1, j = -8..7, float-float")
+    ln2 = mp.log(2)
+    C = ln2 / 256
+    c1 = bits(C, 8, "z")  # rounded toward zero: k c1 exact and x - k c1 exact
+    assert mp.mpf(c1) <= C * (1 - mp.mpf(2) ** -20)
+    c2 = f32(C - c1)
+    c3 = f32(C - c1 - c2)
+    emit_f("SEXP_INV_LN2_256", f32(256 / ln2), "256/ln2")
+    emit_f("SEXP_C1", c1, "ln2/256 truncated to 8 bits")
+    emit_f("SEXP_C2", c2, "next 24 bits of ln2/256")
+    emit_f("SEXP_C3", c3, "next 24 bits of ln2/256")
+    h, l = ff(ln2 / 256)
+    emit_f("SEXP_LN2_256_H", h, "ln2/256 hi")
+    emit_f("SEXP_LN2_256_L", l, "ln2/256 lo")
+    L = 256 * mp.log(10, 2)
+    a = f32(L)
+    b = f32(L - a)
+    c = f32(L - a - b)
+    emit_f("SEXP_L10_H", a, "256 log2(10), three parts")
+    emit_f("SEXP_L10_M", b)
+    emit_f("SEXP_L10_L", c)
+    emit_f("SEXP_INV6", f32(mp.mpf(1) / 6), "1/6")
+    emit_f("SEXP_INV24", f32(mp.mpf(1) / 24), "1/24")
+    emit()
+
+
+def gen_log():
+    emit("// ---- logarithm family, binary32-only ----")
+    # first level: 16 intervals of the mantissa fold m in [0.75, 1.5)
+    c1s = []
+    for j in range(16):
+        if j < 8:
+            lo, hi = 1 + mp.mpf(j) / 16, 1 + mp.mpf(j + 1) / 16
+        else:
+            lo, hi = (1 + mp.mpf(j) / 16) / 2, (1 + mp.mpf(j + 1) / 16) / 2
+        c = 1.0 if j in (0, 15) else bits(2 / (lo + hi), 9, "n")
+        c1s.append(c)
+        t_lo, t_hi = lo * c - 1, hi * c - 1
+        assert -0.0313 <= t_lo and t_hi <= 0.0626, (j, t_lo, t_hi)
+    c2s = [1.0 if i == 0 else bits(1 / (1 + mp.mpf(i) / SLOG_S), 12, "n") for i in range(-8, 8)]
+    emit("// first level: c1 ~ 1/m, 9 bits (1 for the two intervals next to 1)")
+    emit("__device__ __constant__ const float SLOG_C1[16] = {%s};" % ", ".join(fx(c) for c in c1s))
+    emit("// second level: c2 ~ 1/(1 + i/%d), i = -8..7, 12 bits" % SLOG_S)
+    emit("__device__ __constant__ const float SLOG_C2[16] = {%s};" % ", ".join(fx(c) for c in c2s))
+    emit_ff_table("SLOG_L1", [-mp.log(c) for c in c1s], "-log(c1), float-float")
+    emit_ff_table("SLOG_L2", [-mp.log(c) for c in c2s], "-log(c2), float-float")
+    emit_f("SLOG_S", SLOG_S, "second-level index scale")
+    ln2 = mp.log(2)
+    for name, v in (("SLOG_LN2", ln2), ("SLOG_LG2", mp.log(2, 10))):
+        a = bits(v, 16, "n")
+        b = f32(v - a)
+        c = f32(v - a - b)
+        emit_f(name + "_H", a, "16 bits (e times it is exact)")
+        emit_f(name + "_M", b)
+        emit_f(name + "_L", c)
+    for name, v in (("SLOG_INV_LN2", 1 / ln2), ("SLOG_INV_LN10", 1 / mp.log(10)),
+                    ("SLOG_THIRD", mp.mpf(1) / 3)):
+        h, l = ff(v)
+        emit_f(name + "_H", h)
+        emit_f(name + "_L", l)
+    for k in range(4, 8):
+        emit_f("SLOG_P%d" % k, f32(mp.mpf((-1) ** (k + 1)) / k), "(-1)^(k+1)/k")
+    emit()
+
+
+SLOG_S = 112
+
+
+def main():
+    emit("// Generated by paper_2605_15547_amd/gen/gen_split_consts.py -- do not edit.")
+    emit("// Tables and constants of the binary32-only (float-float) kernels.")
+    emit("#pragma once")
+    emit("#include <hip/hip_runtime.h>")
+    emit()
+    gen_exp()
+    gen_log()
+    with open(OUT, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", OUT)
+
+
+if __name__ == "__main__":
+    main()

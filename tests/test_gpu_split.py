@@ -1,0 +1,117 @@
+"""The binary32-only (split, float-float) implementation: bit-exact parity with
+the oracle, and exhaustive agreement of its fast path with the accurate path
+over all 2^32 inputs (needs a GPU)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2605_15547_amd import crmath, inputs  # noqa: E402
+
+from test_gpu_parity import assert_same, gpu_eval  # noqa: E402
+
+SPLIT = crmath.IMPL_SPLIT_F32
+F32 = crmath.FUNCS32
+
+
+def _need(func):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if not crmath.available(func, SPLIT):
+        pytest.skip("no split implementation")
+
+
+@pytest.mark.parametrize("func", F32)
+def test_split_small_sizes_and_unaligned(oracle, func):
+    _need(func)
+    for n, seed in ((1, 1), (5, 2), (2047, 3), (2049, 4), (70001, 5)):
+        x = inputs.workload_f32(func, n, seed=20_000 + seed)
+        assert_same(func, x, gpu_eval(func, x, impl=SPLIT), oracle.evaluate(func, x))
+    x = inputs.workload_f32(func, 5003, seed=21_000)
+    ref = oracle.evaluate(func, x)
+    for oi, oo in ((1, 1), (0, 3)):
+        assert_same(func, x, gpu_eval(func, x, impl=SPLIT, offset_in=oi, offset_out=oo), ref)
+
+
+@pytest.mark.parametrize("func", F32)
+def test_split_hard_set(oracle, func):
+    _need(func)
+    x = inputs.hard_set(func)
+    crmath.stats_reset()
+    assert_same(func, x, gpu_eval(func, x, impl=SPLIT), oracle.evaluate(func, x))
+    assert crmath.stats_read()["escapes"] == 0
+
+
+@pytest.mark.parametrize("func", F32)
+def test_split_special_inputs(oracle, func):
+    _need(func)
+    b = [0x00000000, 0x80000000, 0x7F800000, 0xFF800000, 0x7FC00000, 0xFFC00000,
+         0x7F800001, 0x7FC12345, 0x00000001, 0x80000001, 0x007FFFFF, 0x807FFFFF,
+         0x00800000, 0x80800000, 0x7F7FFFFF, 0xFF7FFFFF, 0x3F800000, 0xBF800000,
+         0x3F000000, 0xBF000000, 0x40000000, 0xC0000000, 0x42B17218, 0x42B17217,
+         0xC2CFF1B5, 0xC2CFF1B4, 0xC3160000, 0xC3150000, 0x42FE0000, 0x43000000,
+         0x4B000000, 0x4B800000, 0x3F800001, 0x3F7FFFFF, 0x33800000, 0xB3800000,
+         0x32000000, 0xB2000000, 0x3FC90FDB, 0x40490FDB, 0x49742400]
+    # binary32 integers and their neighbours: exact cases of exp2f and exp10f
+    ks = np.arange(-160, 131, dtype=np.float32)
+    sp = np.concatenate([np.array(b, dtype=np.uint32).view(np.float32), ks,
+                         np.nextafter(ks, np.float32(np.inf)),
+                         np.nextafter(ks, np.float32(-np.inf))])
+    assert_same(func, sp, gpu_eval(func, sp, impl=SPLIT), oracle.evaluate(func, sp))
+
+
+def test_split_expf_correctness_set(oracle):
+    _need("expf")
+    x = inputs.expf_correctness_set()
+    assert_same("expf", x, gpu_eval("expf", x, impl=SPLIT), oracle.evaluate("expf", x))
+
+
+@pytest.mark.parametrize("func", F32)
+def test_split_full_size_sampled(oracle, func):
+    _need(func)
+    n = 1 << 26
+    x = inputs.workload_f32(func, n)
+    crmath.stats_reset()
+    got = gpu_eval(func, x, impl=SPLIT)
+    st = crmath.stats_read()
+    idx = inputs.Stream(434343).below(1 << 14, n)
+    ref = oracle.evaluate(func, x[idx])
+    assert_same(func, x[idx], got[:, idx] if func == "sincosf" else got[idx], ref)
+    assert st["escapes"] == 0
+
+
+CHUNK = 1 << 28
+
+
+@pytest.mark.parametrize("func", [f for f in F32 if f != "rsqrtf"])
+def test_split_exhaustive_fast_path_matches_accurate_path(func):
+    """Every binary32 encoding: the result the split fast path certifies equals
+    the accurate path's (forced on every element)."""
+    _need(func)
+    sp = crmath._stream_ptr(None)
+    crmath.stats_reset()
+    total_bad, first = 0, None
+    for c in range(1 << 32 >> 28):
+        xi = torch.arange(c * CHUNK, (c + 1) * CHUNK, dtype=torch.int64, device="cuda")
+        x = xi.to(torch.int32).view(torch.float32)
+        del xi
+        n = x.numel()
+        nout = 2 * n if func == "sincosf" else n
+        a = torch.empty(nout, dtype=torch.float32, device="cuda")
+        b = torch.empty(nout, dtype=torch.float32, device="cuda")
+        crmath.eval_ptr(func, x.data_ptr(), a.data_ptr(), n, SPLIT, 0, sp)
+        crmath.eval_ptr(func, x.data_ptr(), b.data_ptr(), n, SPLIT, crmath.FLAG_FORCE_FALLBACK, sp)
+        bad = a.view(torch.int32) != b.view(torch.int32)
+        nb = int(bad.sum().item())
+        if nb and first is None:
+            i = int(torch.nonzero(bad)[0].item()) % CHUNK
+            first = (hex(c * CHUNK + i), hex(int(a.view(torch.int32)[i].item()) & 0xffffffff),
+                     hex(int(b.view(torch.int32)[i].item()) & 0xffffffff))
+        total_bad += nb
+        del a, b, bad, x
+    torch.cuda.synchronize()
+    st = crmath.stats_read()
+    assert total_bad == 0, (func, total_bad, first)
+    assert st["escapes"] == 0, st
