@@ -150,6 +150,10 @@ def main():
     ap.add_argument("--impl", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2605_15547_amd", "tuning",
+                                                      "mi355x.txt"),
+                    help="launch configurations written by paper_2605_15547_amd/autotune.py")
+    ap.add_argument("--no-tuning", action="store_true", help="library default configurations")
     ap.add_argument("--headline-only", action="store_true",
                     help="measure only the exp/log-family step (profiling runs)")
     ap.add_argument("--copy-ref", action="store_true",
@@ -166,6 +170,10 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     crmath.lib()
+    tuning = None
+    if not a.no_tuning and os.path.exists(a.tuning):
+        crmath.tune_load(a.tuning)
+        tuning = os.path.relpath(a.tuning, ROOT)
     dev = torch.device("cuda:0")
     n = 1 << a.n
     funcs = [f for f in FAMILY if crmath.available(f, a.impl)]
@@ -246,6 +254,12 @@ def main():
         extra["binary64_exp_log"] = bench_family(
             torch, crmath, inputs, ["exp", "log"], 1 << 24, 0, a.steps, a.warmup, stream)
         extra["ragged_batch"] = bench_batch(torch, crmath, inputs, a.steps, a.warmup, stream)
+        # the binary32-only (float-float) implementation beside the binary64-internal one
+        extra["exp_log_family_split_f32"] = bench_family(
+            torch, crmath, inputs, FAMILY, n, 2, a.steps, a.warmup, stream)
+        extra["trig_split_f32"] = bench_family(
+            torch, crmath, inputs, ["sinf", "cosf", "sincosf", "tanf"], n, 2, a.steps, a.warmup,
+            stream)
 
     cpu = None
     if not a.no_cpu_baseline:
@@ -275,12 +289,24 @@ def main():
            "dtype": "f64", "data": "synthetic",
            "config": {"workload": "exp/log family, 2^%d binary32 inputs per function" % a.n,
                       "functions": funcs, "missing": missing, "elems_per_function": n,
-                      "impl": "f64_internal" if a.impl in (0, 1) else "split_f32"},
+                      "impl": "f64_internal" if a.impl in (0, 1) else "split_f32",
+                      "tuning": tuning,
+                      "launch": {f: list(crmath.tune_get(f, a.impl)) for f in funcs}},
            "per_func": per,
            "fallback": {"lanes": st["fallback_lanes"], "waves": st["fallback_waves"],
                         "escapes": st["escapes"],
                         "lane_rate": st["fallback_lanes"] / max(1, total_elems)},
            "roofline": roof, "cpu_baseline": cpu, "other_workloads": extra}
+    sp = extra.get("exp_log_family_split_f32")
+    if sp:
+        both = [f for f in funcs if sp["per_func"].get(f)]
+        t_split = sum(sp["per_func"][f]["ms"] for f in both)
+        t_f64 = sum(per[f]["ms"] for f in both)
+        rec["split_f32_vs_f64"] = {
+            "functions": both,
+            "split_gelem_s": round(len(both) * n / (t_split * 1e-3) / 1e9, 2),
+            "f64_gelem_s": round(len(both) * n / (t_f64 * 1e-3) / 1e9, 2),
+            "ratio": round(t_f64 / t_split, 3)}
     if copy_ms is not None:
         rec["copy_ref"] = {"ms": round(copy_ms, 4), "bytes": 8 * n,
                            "gb_s": round(8 * n / (copy_ms * 1e-3) / 1e9, 1)}

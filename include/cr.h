@@ -79,7 +79,8 @@ enum cr_status {
   CR_E_IMPL = -5,    /* unknown or unavailable implementation */
   CR_E_HIP = -6,     /* a HIP runtime call failed; see cr_last_hip_error() */
   CR_E_NOMEM = -7,   /* device allocation of library state failed */
-  CR_E_SIZE = -9     /* n too large */
+  CR_E_SIZE = -9,    /* n too large */
+  CR_E_TUNE = -10    /* invalid launch configuration, or unreadable/malformed tuning file */
 };
 
 /* out[i] = RN(f(in[i])) for i < n, func = func_id, default implementation.
@@ -159,6 +160,46 @@ typedef struct {
 int cr_stats_reset(void *stream);
 /* Copy the current device's counters to *out; synchronises the stream. */
 int cr_stats_read(void *stream, cr_stats *out);
+
+/* ---- Launch configurations and the autotuner --------------------------------
+ * The project's own addition beside the paper's kernels: how a function's
+ * elementwise kernel is laid out on the GPU.  Each (function, implementation)
+ * pair has one configuration: a kernel variant -- elements per thread (4, 8
+ * or 16 binary32 values, i.e. 1, 2 or 4 float4 loads per tile), whether the
+ * next tile is loaded while the current one is evaluated (software
+ * pipelining), and where the function's <= 16-entry tables live (staged in
+ * LDS per workgroup, or read from one device-global copy through the vector
+ * caches) -- and the persistent grid size in workgroups per compute unit.
+ * Results never depend on the configuration, only speed does.  sincosf and
+ * the binary64 functions have variant 0 only (their grid is tunable).
+ * Configurations are process-wide host state shared by all devices. */
+typedef struct {
+  int32_t variant;       /* 0 .. cr_tune_num_variants()-1; 0 is the default */
+  int32_t blocks_per_cu; /* 1..64; 0 (set only) = the library default (16) */
+} cr_tune_cfg;
+
+int cr_tune_num_variants(void);
+/* Shape of a variant; any output pointer may be NULL.  CR_E_TUNE if out of range. */
+int cr_tune_variant_info(int variant, int *elems_per_thread, int *prefetch, int *table_in_lds);
+/* Current configuration of (func_id, impl); CR_IMPL_AUTO means F64_INTERNAL. */
+int cr_tune_get(int func_id, int impl, cr_tune_cfg *cfg);
+/* Install a configuration.  CR_E_FUNC / CR_E_IMPL / CR_E_NULL / CR_E_TUNE on bad input. */
+int cr_tune_set(int func_id, int impl, const cr_tune_cfg *cfg);
+/* All configurations back to the defaults. */
+int cr_tune_reset(void);
+/* Text file, one line per entry: "<function> <f64|split> <variant> <blocks_per_cu>";
+ * '#' starts a comment line.  Load applies nothing unless the whole file is
+ * valid (CR_E_TUNE otherwise); save writes every entry. */
+int cr_tune_load(const char *path);
+int cr_tune_save(const char *path);
+/* Time every variant x grid size {2, 4, 8, 16, 32 workgroups per CU} of
+ * (func_id, impl) on the caller's device buffers in/out (n elements, the same
+ * conventions as cr_eval_ex; out is overwritten), reps timed launches each
+ * after one warm-up (reps <= 0: 5), and install the fastest.  Synchronizes
+ * the stream; adds its launches to the statistics counters.  best_gelem_s
+ * (may be NULL) receives the winner's rate in 10^9 elements per second. */
+int cr_autotune(int func_id, int impl, const void *in, void *out, size_t n, int reps,
+                void *stream, double *best_gelem_s);
 
 /* Human-readable text for a status code (static storage). */
 const char *cr_status_str(int status);

@@ -22,11 +22,13 @@ FLAG_FORCE_FALLBACK = 1
 
 CR_OK = 0
 STATUS = {0: "CR_OK", -1: "CR_E_FUNC", -2: "CR_E_NULL", -3: "CR_E_OVERLAP", -4: "CR_E_ALIGN",
-          -5: "CR_E_IMPL", -6: "CR_E_HIP", -7: "CR_E_NOMEM", -9: "CR_E_SIZE"}
+          -5: "CR_E_IMPL", -6: "CR_E_HIP", -7: "CR_E_NOMEM", -9: "CR_E_SIZE", -10: "CR_E_TUNE"}
 
 EXPORTED = ["cr_eval", "cr_eval_ex", "cr_available", "cr_batch_plan_create",
             "cr_batch_plan_launch", "cr_batch_plan_destroy", "cr_eval_batch", "cr_stats_reset",
-            "cr_stats_read", "cr_status_str", "cr_last_hip_error"]
+            "cr_stats_read", "cr_status_str", "cr_last_hip_error", "cr_tune_num_variants",
+            "cr_tune_variant_info", "cr_tune_get", "cr_tune_set", "cr_tune_reset", "cr_tune_load",
+            "cr_tune_save", "cr_autotune"]
 
 
 class CrError(RuntimeError):
@@ -39,6 +41,11 @@ class Request(ctypes.Structure):
     """cr_request: one entry of a batch (device pointers as integers)."""
     _fields_ = [("func_id", ctypes.c_int32), ("impl", ctypes.c_int32),
                 ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+class TuneCfg(ctypes.Structure):
+    """cr_tune_cfg: a kernel variant and the grid in workgroups per compute unit."""
+    _fields_ = [("variant", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -75,6 +82,15 @@ def lib():
         L.cr_status_str.argtypes = [ctypes.c_int]
         L.cr_status_str.restype = ctypes.c_char_p
         L.cr_last_hip_error.restype = ctypes.c_int
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.cr_tune_num_variants.restype = ctypes.c_int
+        L.cr_tune_variant_info.argtypes = [ctypes.c_int, ip, ip, ip]
+        L.cr_tune_get.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(TuneCfg)]
+        L.cr_tune_set.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(TuneCfg)]
+        L.cr_tune_load.argtypes = [ctypes.c_char_p]
+        L.cr_tune_save.argtypes = [ctypes.c_char_p]
+        L.cr_autotune.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, sz, ctypes.c_int, vp,
+                                  ctypes.POINTER(ctypes.c_double)]
         _lib = L
     return _lib
 
@@ -175,3 +191,59 @@ def stats_read(stream=None):
     return {"elems": s.elems, "fallback_lanes": s.fallback_lanes,
             "fallback_waves": s.fallback_waves, "escapes": s.escapes,
             "escape_index": list(s.escape_index)[:min(16, s.escapes)]}
+
+
+# ------------------------------------------------------------------ tuning
+def tune_variants():
+    """[(elems_per_thread, prefetch, table_in_lds)] of every kernel variant."""
+    L = lib()
+    out = []
+    for v in range(L.cr_tune_num_variants()):
+        e, p, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        rc = L.cr_tune_variant_info(v, ctypes.byref(e), ctypes.byref(p), ctypes.byref(t))
+        if rc != CR_OK:
+            raise CrError(rc, "cr_tune_variant_info")
+        out.append((e.value, p.value, t.value))
+    return out
+
+
+def tune_get(func, impl=IMPL_AUTO):
+    c = TuneCfg()
+    rc = lib().cr_tune_get(_fid(func), impl, ctypes.byref(c))
+    if rc != CR_OK:
+        raise CrError(rc, "cr_tune_get")
+    return c.variant, c.blocks_per_cu
+
+
+def tune_set(func, impl, variant, blocks_per_cu):
+    c = TuneCfg(variant, blocks_per_cu)
+    rc = lib().cr_tune_set(_fid(func), impl, ctypes.byref(c))
+    if rc != CR_OK:
+        raise CrError(rc, "cr_tune_set")
+
+
+def tune_reset():
+    lib().cr_tune_reset()
+
+
+def tune_load(path):
+    rc = lib().cr_tune_load(os.fsencode(path))
+    if rc != CR_OK:
+        raise CrError(rc, "cr_tune_load")
+
+
+def tune_save(path):
+    rc = lib().cr_tune_save(os.fsencode(path))
+    if rc != CR_OK:
+        raise CrError(rc, "cr_tune_save")
+
+
+def autotune(func, impl, in_ptr, out_ptr, n, reps=5, stream_ptr=None):
+    """Time every launch configuration on the given device buffers, install
+    the fastest and return its rate (Gelem/s)."""
+    best = ctypes.c_double()
+    rc = lib().cr_autotune(_fid(func), impl, in_ptr, out_ptr, n, reps, stream_ptr,
+                           ctypes.byref(best))
+    if rc != CR_OK:
+        raise CrError(rc, "cr_autotune")
+    return best.value

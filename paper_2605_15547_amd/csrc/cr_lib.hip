@@ -8,7 +8,9 @@
 // aligned, and ragged tails, go through a scalar grid-stride kernel.
 #include <hip/hip_runtime.h>
 
+#include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <algorithm>
 #include <atomic>
@@ -25,6 +27,7 @@
 #include "cr_f64.h"
 #include "cr_split_exp.h"
 #include "cr_split_log.h"
+#include "cr_split_trig.h"
 
 using namespace cr;
 
@@ -110,6 +113,43 @@ struct OpExp {
   }
   static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
     return exp_accurate<K>(x, t);
+  }
+};
+
+// sincos: two outputs per element (planar)
+struct SinCosF64 {
+  using Tab = TrigTab;
+  static constexpr int qcheck = QCHECK;
+  static __device__ __forceinline__ void load(Tab& t, int tid) { trig_tab_load(t, tid); }
+  static __device__ __forceinline__ float fast(float x, const Tab& t, float& c, bool& ok) {
+    return sincos_fast(x, t, c, ok);
+  }
+  static __device__ __forceinline__ AccResult2 accurate(float x, const Tab& t) {
+    return sincos_accurate(x, t);
+  }
+};
+struct SinCosSplit {
+  using Tab = STrigTab;
+  static constexpr int qcheck = 1;
+  static __device__ __forceinline__ void load(Tab& t, int tid) { strig_tab_load(t, tid); }
+  static __device__ __forceinline__ float fast(float x, const Tab& t, float& c, bool& ok) {
+    return ssincos_fast(x, t, c, ok);
+  }
+  static __device__ __forceinline__ AccResult2 accurate(float x, const Tab& t) {
+    return sincos_accurate(x, t.acc);
+  }
+};
+
+template <int KIND>
+struct OpSTrig {
+  using Tab = STrigTab;
+  static constexpr int qcheck = 1;  // more lanes fail: look at the queue every tile
+  static __device__ __forceinline__ void load(Tab& t, int tid) { strig_tab_load(t, tid); }
+  static __device__ __forceinline__ float fast(float x, const Tab& t, bool& ok) {
+    return strig_fast<KIND>(x, t, ok);
+  }
+  static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
+    return trig_accurate<KIND>(x, t.acc);
   }
 };
 
@@ -254,13 +294,27 @@ __device__ __noinline__ void flush_queue(Deferred& q, const typename Op::Tab& ta
 // input value) and re-evaluated by the accurate path a whole workgroup at a
 // time -- when the queue passes QFLUSH and at the end -- so a rare failing
 // lane does not make a 64-lane wave run the slow path for it alone.
+// Launch-shape variants (chosen per function by the autotuner, cr_autotune):
+//   U   float4 vectors per thread per tile (4U elements per thread),
+//   PF  1: the next tile's vectors are loaded while this one is evaluated,
+//   TP  table placement: 0 = staged in LDS per workgroup, 1 = read from a
+//       device-global copy through the vector caches (no staging).
 template <class Op>
+__device__ typename Op::Tab g_tab;
+
+template <class Op>
+__global__ void k_tab_init() {
+  Op::load(g_tab<Op>, threadIdx.x);
+}
+
+template <class Op, int U, int PF, int TP>
 __global__ void __launch_bounds__(BLOCK)
     k_map_f32(const float4* in, float4* out, long long n4, DevStats* st,
               unsigned flags, long long elem_base) {
-  __shared__ typename Op::Tab tab;
+  __shared__ typename Op::Tab lds_tab;
   __shared__ Deferred q;
-  Op::load(tab, threadIdx.x);
+  const typename Op::Tab& tab = TP ? g_tab<Op> : lds_tab;
+  if (!TP) Op::load(lds_tab, threadIdx.x);
   if (threadIdx.x == 0) {
     q.n = 0;
     q.lanes = q.waves = q.esc = 0;
@@ -268,42 +322,42 @@ __global__ void __launch_bounds__(BLOCK)
   __syncthreads();
   const bool force = flags & CR_FLAG_FORCE_FALLBACK;
   float* outf = reinterpret_cast<float*>(out);
-  const long long ntiles = (n4 + BLOCK * TILE_U - 1) / (BLOCK * TILE_U);
+  const long long ntiles = (n4 + BLOCK * U - 1) / (BLOCK * U);
   // software pipelining: the next tile's vectors are loaded while this tile
   // is evaluated
-  float4 nxt[TILE_U];
-  if (CR_PREFETCH) {
-    long long base = (long long)blockIdx.x * (BLOCK * TILE_U) + threadIdx.x;
+  float4 nxt[U];
+  if (PF) {
+    long long base = (long long)blockIdx.x * (BLOCK * U) + threadIdx.x;
 #pragma unroll
-    for (int u = 0; u < TILE_U; u++) {
+    for (int u = 0; u < U; u++) {
       long long i = base + (long long)u * BLOCK;
       if (i < n4) nxt[u] = ld_stream(in + i);
     }
   }
   int iter = 0;
   for (long long t = blockIdx.x; t < ntiles; t += gridDim.x, iter++) {
-    long long base = t * (BLOCK * TILE_U) + threadIdx.x;
-    float4 v[TILE_U];
-    if (CR_PREFETCH) {
+    long long base = t * (BLOCK * U) + threadIdx.x;
+    float4 v[U];
+    if (PF) {
 #pragma unroll
-      for (int u = 0; u < TILE_U; u++) v[u] = nxt[u];
+      for (int u = 0; u < U; u++) v[u] = nxt[u];
     } else {
 #pragma unroll
-      for (int u = 0; u < TILE_U; u++) {
+      for (int u = 0; u < U; u++) {
         long long i = base + (long long)u * BLOCK;
         if (i < n4) v[u] = ld_stream(in + i);
       }
     }
-    if (CR_PREFETCH) {
-      long long nb = (t + gridDim.x) * (BLOCK * TILE_U) + threadIdx.x;
+    if (PF) {
+      long long nb = (t + gridDim.x) * (BLOCK * U) + threadIdx.x;
 #pragma unroll
-      for (int u = 0; u < TILE_U; u++) {
+      for (int u = 0; u < U; u++) {
         long long i = nb + (long long)u * BLOCK;
         if (i < n4) nxt[u] = ld_stream(in + i);
       }
     }
 #pragma unroll
-    for (int u = 0; u < TILE_U; u++) {
+    for (int u = 0; u < U; u++) {
       long long i = base + (long long)u * BLOCK;
       if (i < n4) {
         float* e = reinterpret_cast<float*>(&v[u]);
@@ -331,7 +385,7 @@ __global__ void __launch_bounds__(BLOCK)
       }
     }
 #pragma unroll
-    for (int u = 0; u < TILE_U; u++) {
+    for (int u = 0; u < U; u++) {
       long long i = base + (long long)u * BLOCK;
       if (i < n4) st_stream(out + i, v[u]);
     }
@@ -387,11 +441,12 @@ __global__ void __launch_bounds__(BLOCK)
 
 // sincosf: the map kernel with two planar outputs (sin block, cos block), both
 // 16-byte aligned (the host checks; otherwise the scalar form below runs).
-__device__ __noinline__ void flush_queue_sincos(Deferred& q, const TrigTab& tab, float* os,
+template <class SC>
+__device__ __noinline__ void flush_queue_sincos(Deferred& q, const typename SC::Tab& tab, float* os,
                                                 float* oc, DevStats* st, long long elem_base) {
   unsigned n = q.n < QCAP ? q.n : QCAP;
   for (unsigned k = threadIdx.x; k < n; k += BLOCK) {
-    AccResult2 a = sincos_accurate(q.x[k], tab);
+    AccResult2 a = SC::accurate(q.x[k], tab);
     os[q.idx[k]] = a.s;
     oc[q.idx[k]] = a.c;
     if (!a.ok) {
@@ -408,12 +463,13 @@ __device__ __noinline__ void flush_queue_sincos(Deferred& q, const TrigTab& tab,
   __syncthreads();
 }
 
+template <class SC>
 __global__ void __launch_bounds__(BLOCK)
     k_map_sincos(const float4* in, float4* outs, float4* outc, long long n4, DevStats* st,
                  unsigned flags, long long elem_base) {
-  __shared__ TrigTab tab;
+  __shared__ typename SC::Tab tab;
   __shared__ Deferred q;
-  trig_tab_load(tab, threadIdx.x);
+  SC::load(tab, threadIdx.x);
   if (threadIdx.x == 0) {
     q.n = 0;
     q.lanes = q.waves = q.esc = 0;
@@ -440,14 +496,14 @@ __global__ void __launch_bounds__(BLOCK)
         for (int c = 0; c < 4; c++) {
           bool ok;
           float x = e[c];
-          e[c] = sincos_fast(x, tab, ec[c], ok);
+          e[c] = SC::fast(x, tab, ec[c], ok);
           if (!ok || force) {
             unsigned pos = atomicAdd(&q.n, 1u);
             if (pos < QCAP) {
               q.idx[pos] = (unsigned)(4 * i + c);
               q.x[pos] = x;
             } else {
-              AccResult2 a = sincos_accurate(x, tab);
+              AccResult2 a = SC::accurate(x, tab);
               e[c] = a.s;
               ec[c] = a.c;
               atomicAdd(&q.lanes, 1u);
@@ -468,18 +524,18 @@ __global__ void __launch_bounds__(BLOCK)
         st_stream(outc + i, c4[u]);
       }
     }
-    if (iter % QCHECK == QCHECK - 1) {
+    if (iter % SC::qcheck == SC::qcheck - 1) {
       __syncthreads();
       const unsigned nq = q.n;
       __syncthreads();
       if (nq > QFLUSH)
-        flush_queue_sincos(q, tab, reinterpret_cast<float*>(outs), reinterpret_cast<float*>(outc),
+        flush_queue_sincos<SC>(q, tab, reinterpret_cast<float*>(outs), reinterpret_cast<float*>(outc),
                            st, elem_base);
     }
   }
   __syncthreads();
   if (q.n)
-    flush_queue_sincos(q, tab, reinterpret_cast<float*>(outs), reinterpret_cast<float*>(outc), st,
+    flush_queue_sincos<SC>(q, tab, reinterpret_cast<float*>(outs), reinterpret_cast<float*>(outc), st,
                        elem_base);
   if (threadIdx.x == 0 && q.lanes) {
     CounterSlot& c = st->slot[blockIdx.x % NSLOT];
@@ -488,11 +544,12 @@ __global__ void __launch_bounds__(BLOCK)
   }
 }
 
+template <class SC>
 __global__ void __launch_bounds__(BLOCK)
     k_map_sincos_scalar(const float* in, float* outs, float* outc, long long n, DevStats* st,
                         unsigned flags, long long elem_base) {
-  __shared__ TrigTab tab;
-  trig_tab_load(tab, threadIdx.x);
+  __shared__ typename SC::Tab tab;
+  SC::load(tab, threadIdx.x);
   __syncthreads();
   const bool force = flags & CR_FLAG_FORCE_FALLBACK;
   unsigned lanes = 0;
@@ -500,9 +557,9 @@ __global__ void __launch_bounds__(BLOCK)
        i += (long long)gridDim.x * BLOCK) {
     bool ok;
     float x = in[i], c;
-    float s = sincos_fast(x, tab, c, ok);
+    float s = SC::fast(x, tab, c, ok);
     if (!ok || force) {
-      AccResult2 a = sincos_accurate(x, tab);
+      AccResult2 a = SC::accurate(x, tab);
       s = a.s;
       c = a.c;
       lanes++;
@@ -985,25 +1042,57 @@ int get_stats(DevStats** out) {
   return CR_OK;
 }
 
-int g_grid_blocks = 0;  // persistent grid size (workgroups), set on first use
+int g_cus = 0;  // compute units of the current device (cached on first use)
 
-int grid_blocks() {
-  if (!g_grid_blocks) {
+int num_cus() {
+  if (!g_cus) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
       (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    int per = CR_BLOCKS_PER_CU;
-    if (const char* e = getenv("CR_BLOCKS_PER_CU")) per = atoi(e);
-    if (per < 1) per = 1;
-    if (per > 64) per = 64;
-    g_grid_blocks = cus * per;
+    g_cus = cus > 0 ? cus : 256;
   }
-  return g_grid_blocks;
+  return g_cus;
 }
 
+// default workgroups per compute unit of the persistent grids
+int default_bpc() {
+  static int per = 0;
+  if (!per) {
+    int v = CR_BLOCKS_PER_CU;
+    if (const char* e = getenv("CR_BLOCKS_PER_CU")) v = atoi(e);
+    per = v < 1 ? 1 : (v > 64 ? 64 : v);
+  }
+  return per;
+}
+
+int grid_blocks() { return num_cus() * default_bpc(); }
+
+// The table copy read by the global-placement variants, filled once per device
+// (synchronously, on first use).
 template <class Op>
+int ensure_gtab() {
+  static std::atomic<unsigned long long> done{0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  const unsigned long long bit = 1ull << (dev & 63);
+  if (done.load() & bit) return CR_OK;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (done.load() & bit) return CR_OK;
+  hipLaunchKernelGGL(k_tab_init<Op>, dim3(1), dim3(BLOCK), 0, 0);
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e);
+  done |= bit;
+  return CR_OK;
+}
+
+template <class Op, int U, int PF, int TP>
 int launch_map_f32(const float* in, float* out, size_t n, hipStream_t s, unsigned flags,
-                   DevStats* st) {
+                   DevStats* st, int grid) {
+  if (TP) {
+    int rc = ensure_gtab<Op>();
+    if (rc) return rc;
+  }
   uintptr_t ai = (uintptr_t)in, ao = (uintptr_t)out;
   size_t head = 0;
   if ((ai & 15) == (ao & 15)) {
@@ -1024,10 +1113,10 @@ int launch_map_f32(const float* in, float* out, size_t n, hipStream_t s, unsigne
   for (size_t done = 0; done < body4;) {
     size_t chunk4 = body4 - done;
     if (chunk4 > ((size_t)1 << 29)) chunk4 = (size_t)1 << 29;
-    size_t tiles = (chunk4 + BLOCK * TILE_U - 1) / (BLOCK * TILE_U);
-    size_t g = tiles < (size_t)grid_blocks() ? tiles : (size_t)grid_blocks();
+    size_t tiles = (chunk4 + BLOCK * U - 1) / (BLOCK * U);
+    size_t g = tiles < (size_t)grid ? tiles : (size_t)grid;
     size_t off = head + 4 * done;
-    hipLaunchKernelGGL(k_map_f32<Op>, dim3((unsigned)g), dim3(BLOCK), 0, s,
+    hipLaunchKernelGGL((k_map_f32<Op, U, PF, TP>), dim3((unsigned)g), dim3(BLOCK), 0, s,
                        reinterpret_cast<const float4*>(in + off),
                        reinterpret_cast<float4*>(out + off), (long long)chunk4, st, flags,
                        (long long)off);
@@ -1043,8 +1132,29 @@ int launch_map_f32(const float* in, float* out, size_t n, hipStream_t s, unsigne
   return CR_OK;
 }
 
+// The launch variants the autotuner chooses from: {U, PF, TP} of k_map_f32.
+constexpr int NVARIANT = 7;
+constexpr int VARIANTS[NVARIANT][3] = {{2, 1, 0}, {1, 1, 0}, {4, 1, 0}, {2, 0, 0},
+                                       {4, 0, 0}, {1, 0, 0}, {2, 1, 1}};
+
+template <class Op>
+int launch_variant(const float* in, float* out, size_t n, hipStream_t s, unsigned flags,
+                   DevStats* st, int variant, int grid) {
+  switch (variant) {
+    case 0: return launch_map_f32<Op, 2, 1, 0>(in, out, n, s, flags, st, grid);
+    case 1: return launch_map_f32<Op, 1, 1, 0>(in, out, n, s, flags, st, grid);
+    case 2: return launch_map_f32<Op, 4, 1, 0>(in, out, n, s, flags, st, grid);
+    case 3: return launch_map_f32<Op, 2, 0, 0>(in, out, n, s, flags, st, grid);
+    case 4: return launch_map_f32<Op, 4, 0, 0>(in, out, n, s, flags, st, grid);
+    case 5: return launch_map_f32<Op, 1, 0, 0>(in, out, n, s, flags, st, grid);
+    case 6: return launch_map_f32<Op, 2, 1, 1>(in, out, n, s, flags, st, grid);
+  }
+  return CR_E_TUNE;
+}
+
+template <class SC>
 int launch_sincos(const float* in, float* out, size_t n, hipStream_t s, unsigned flags,
-                  DevStats* st) {
+                  DevStats* st, int grid) {
   float* outc = out + n;
   uintptr_t ai = (uintptr_t)in, ao = (uintptr_t)out, ac = (uintptr_t)outc;
   bool vec = (ai & 15) == 0 && (ao & 15) == 0 && (ac & 15) == 0;
@@ -1054,9 +1164,9 @@ int launch_sincos(const float* in, float* out, size_t n, hipStream_t s, unsigned
     size_t chunk4 = body4 - done4;
     if (chunk4 > ((size_t)1 << 29)) chunk4 = (size_t)1 << 29;
     size_t tiles = (chunk4 + BLOCK * TILE_U - 1) / (BLOCK * TILE_U);
-    size_t g = tiles < (size_t)grid_blocks() ? tiles : (size_t)grid_blocks();
+    size_t g = tiles < (size_t)grid ? tiles : (size_t)grid;
     size_t off = 4 * done4;
-    hipLaunchKernelGGL(k_map_sincos, dim3((unsigned)g), dim3(BLOCK), 0, s,
+    hipLaunchKernelGGL(k_map_sincos<SC>, dim3((unsigned)g), dim3(BLOCK), 0, s,
                        reinterpret_cast<const float4*>(in + off),
                        reinterpret_cast<float4*>(out + off), reinterpret_cast<float4*>(outc + off),
                        (long long)chunk4, st, flags, (long long)off);
@@ -1067,7 +1177,7 @@ int launch_sincos(const float* in, float* out, size_t n, hipStream_t s, unsigned
     size_t rest = n - off;
     size_t g = (rest + BLOCK - 1) / BLOCK;
     if (g > 65536) g = 65536;
-    hipLaunchKernelGGL(k_map_sincos_scalar, dim3((unsigned)g), dim3(BLOCK), 0, s, in + off,
+    hipLaunchKernelGGL(k_map_sincos_scalar<SC>, dim3((unsigned)g), dim3(BLOCK), 0, s, in + off,
                        out + off, outc + off, (long long)rest, st, flags, (long long)off);
   }
   hipError_t e = hipGetLastError();
@@ -1077,7 +1187,7 @@ int launch_sincos(const float* in, float* out, size_t n, hipStream_t s, unsigned
 
 template <class Op>
 int launch_map_f64(const double* in, double* out, size_t n, hipStream_t s, unsigned flags,
-                   DevStats* st) {
+                   DevStats* st, int grid) {
   uintptr_t ai = (uintptr_t)in, ao = (uintptr_t)out;
   size_t head = 0;
   if ((ai & 15) == (ao & 15)) {
@@ -1098,7 +1208,7 @@ int launch_map_f64(const double* in, double* out, size_t n, hipStream_t s, unsig
     size_t chunk2 = body2 - done;
     if (chunk2 > ((size_t)1 << 30)) chunk2 = (size_t)1 << 30;
     size_t tiles = (chunk2 + BLOCK * TILE64_U - 1) / (BLOCK * TILE64_U);
-    size_t g = tiles < (size_t)grid_blocks() ? tiles : (size_t)grid_blocks();
+    size_t g = tiles < (size_t)grid ? tiles : (size_t)grid;
     size_t off = head + 2 * done;
     hipLaunchKernelGGL(k_map_f64<Op>, dim3((unsigned)g), dim3(BLOCK), 0, s,
                        reinterpret_cast<const double2*>(in + off),
@@ -1119,49 +1229,96 @@ int launch_map_f64(const double* in, double* out, size_t n, hipStream_t s, unsig
 bool func_valid(int f) { return (f >= 0 && f < CR_NUM_F32) || f == CR_EXP || f == CR_LOG; }
 bool func_built(int f) { return (f >= CR_EXPF && f <= CR_TANHF) || f == CR_EXP || f == CR_LOG; }
 // functions with a binary32-only (split) implementation
-bool split_built(int f) { return f >= CR_EXPF && f <= CR_LOG1PF; }
+bool split_built(int f) { return (f >= CR_EXPF && f <= CR_LOG1PF) || (f >= CR_SINF && f <= CR_TANF); }
 
 int dispatch_f32_split(int f, const float* in, float* out, size_t n, hipStream_t s,
-                       unsigned flags, DevStats* st) {
+                       unsigned flags, DevStats* st, int v, int g) {
   switch (f) {
-    case CR_EXPF: return launch_map_f32<OpSExp<EXPK_E>>(in, out, n, s, flags, st);
-    case CR_EXP2F: return launch_map_f32<OpSExp<EXPK_2>>(in, out, n, s, flags, st);
-    case CR_EXP10F: return launch_map_f32<OpSExp<EXPK_10>>(in, out, n, s, flags, st);
-    case CR_EXPM1F: return launch_map_f32<OpSExp<EXPK_EM1>>(in, out, n, s, flags, st);
-    case CR_LOGF: return launch_map_f32<OpSLog<LOGK_E>>(in, out, n, s, flags, st);
-    case CR_LOG2F: return launch_map_f32<OpSLog<LOGK_2>>(in, out, n, s, flags, st);
-    case CR_LOG10F: return launch_map_f32<OpSLog<LOGK_10>>(in, out, n, s, flags, st);
-    case CR_LOG1PF: return launch_map_f32<OpSLog<LOGK_1P>>(in, out, n, s, flags, st);
+    case CR_EXPF: return launch_variant<OpSExp<EXPK_E>>(in, out, n, s, flags, st, v, g);
+    case CR_EXP2F: return launch_variant<OpSExp<EXPK_2>>(in, out, n, s, flags, st, v, g);
+    case CR_EXP10F: return launch_variant<OpSExp<EXPK_10>>(in, out, n, s, flags, st, v, g);
+    case CR_EXPM1F: return launch_variant<OpSExp<EXPK_EM1>>(in, out, n, s, flags, st, v, g);
+    case CR_LOGF: return launch_variant<OpSLog<LOGK_E>>(in, out, n, s, flags, st, v, g);
+    case CR_LOG2F: return launch_variant<OpSLog<LOGK_2>>(in, out, n, s, flags, st, v, g);
+    case CR_LOG10F: return launch_variant<OpSLog<LOGK_10>>(in, out, n, s, flags, st, v, g);
+    case CR_LOG1PF: return launch_variant<OpSLog<LOGK_1P>>(in, out, n, s, flags, st, v, g);
+    case CR_SINF: return launch_variant<OpSTrig<TRIGK_SIN>>(in, out, n, s, flags, st, v, g);
+    case CR_COSF: return launch_variant<OpSTrig<TRIGK_COS>>(in, out, n, s, flags, st, v, g);
+    case CR_TANF: return launch_variant<OpSTrig<TRIGK_TAN>>(in, out, n, s, flags, st, v, g);
+    case CR_SINCOSF: return launch_sincos<SinCosSplit>(in, out, n, s, flags, st, g);
   }
   return CR_E_IMPL;
 }
 
 int dispatch_f32(int f, const float* in, float* out, size_t n, hipStream_t s, unsigned flags,
-                 DevStats* st) {
+                 DevStats* st, int v, int g) {
   switch (f) {
-    case CR_EXPF: return launch_map_f32<OpExp<EXPK_E>>(in, out, n, s, flags, st);
-    case CR_EXP2F: return launch_map_f32<OpExp<EXPK_2>>(in, out, n, s, flags, st);
-    case CR_EXP10F: return launch_map_f32<OpExp<EXPK_10>>(in, out, n, s, flags, st);
-    case CR_EXPM1F: return launch_map_f32<OpExp<EXPK_EM1>>(in, out, n, s, flags, st);
-    case CR_LOGF: return launch_map_f32<OpLog<LOGK_E>>(in, out, n, s, flags, st);
-    case CR_LOG2F: return launch_map_f32<OpLog<LOGK_2>>(in, out, n, s, flags, st);
-    case CR_LOG10F: return launch_map_f32<OpLog<LOGK_10>>(in, out, n, s, flags, st);
-    case CR_LOG1PF: return launch_map_f32<OpLog<LOGK_1P>>(in, out, n, s, flags, st);
-    case CR_RSQRTF: return launch_map_f32<OpRsqrt>(in, out, n, s, flags, st);
-    case CR_SINF: return launch_map_f32<OpTrig<TRIGK_SIN>>(in, out, n, s, flags, st);
-    case CR_COSF: return launch_map_f32<OpTrig<TRIGK_COS>>(in, out, n, s, flags, st);
-    case CR_TANF: return launch_map_f32<OpTrig<TRIGK_TAN>>(in, out, n, s, flags, st);
-    case CR_SINCOSF: return launch_sincos(in, out, n, s, flags, st);
-    case CR_ASINF: return launch_map_f32<OpAtan<ATANK_ASIN>>(in, out, n, s, flags, st);
-    case CR_ACOSF: return launch_map_f32<OpAtan<ATANK_ACOS>>(in, out, n, s, flags, st);
-    case CR_ATANF: return launch_map_f32<OpAtan<ATANK_ATAN>>(in, out, n, s, flags, st);
-    case CR_SINHF: return launch_map_f32<OpHyp<HYPK_SINH>>(in, out, n, s, flags, st);
-    case CR_COSHF: return launch_map_f32<OpHyp<HYPK_COSH>>(in, out, n, s, flags, st);
-    case CR_TANHF: return launch_map_f32<OpHyp<HYPK_TANH>>(in, out, n, s, flags, st);
+    case CR_EXPF: return launch_variant<OpExp<EXPK_E>>(in, out, n, s, flags, st, v, g);
+    case CR_EXP2F: return launch_variant<OpExp<EXPK_2>>(in, out, n, s, flags, st, v, g);
+    case CR_EXP10F: return launch_variant<OpExp<EXPK_10>>(in, out, n, s, flags, st, v, g);
+    case CR_EXPM1F: return launch_variant<OpExp<EXPK_EM1>>(in, out, n, s, flags, st, v, g);
+    case CR_LOGF: return launch_variant<OpLog<LOGK_E>>(in, out, n, s, flags, st, v, g);
+    case CR_LOG2F: return launch_variant<OpLog<LOGK_2>>(in, out, n, s, flags, st, v, g);
+    case CR_LOG10F: return launch_variant<OpLog<LOGK_10>>(in, out, n, s, flags, st, v, g);
+    case CR_LOG1PF: return launch_variant<OpLog<LOGK_1P>>(in, out, n, s, flags, st, v, g);
+    case CR_RSQRTF: return launch_variant<OpRsqrt>(in, out, n, s, flags, st, v, g);
+    case CR_SINF: return launch_variant<OpTrig<TRIGK_SIN>>(in, out, n, s, flags, st, v, g);
+    case CR_COSF: return launch_variant<OpTrig<TRIGK_COS>>(in, out, n, s, flags, st, v, g);
+    case CR_TANF: return launch_variant<OpTrig<TRIGK_TAN>>(in, out, n, s, flags, st, v, g);
+    case CR_SINCOSF: return launch_sincos<SinCosF64>(in, out, n, s, flags, st, g);
+    case CR_ASINF: return launch_variant<OpAtan<ATANK_ASIN>>(in, out, n, s, flags, st, v, g);
+    case CR_ACOSF: return launch_variant<OpAtan<ATANK_ACOS>>(in, out, n, s, flags, st, v, g);
+    case CR_ATANF: return launch_variant<OpAtan<ATANK_ATAN>>(in, out, n, s, flags, st, v, g);
+    case CR_SINHF: return launch_variant<OpHyp<HYPK_SINH>>(in, out, n, s, flags, st, v, g);
+    case CR_COSHF: return launch_variant<OpHyp<HYPK_COSH>>(in, out, n, s, flags, st, v, g);
+    case CR_TANHF: return launch_variant<OpHyp<HYPK_TANH>>(in, out, n, s, flags, st, v, g);
   }
   return CR_E_FUNC;
 }
 
+
+// ------------------------------------------------------------ tuning table
+// One launch configuration per (implementation, function): a k_map_f32
+// variant and the persistent grid in workgroups per compute unit.  Index 0 of
+// the first dimension is the binary64-internal implementation (and AUTO), 1
+// the split one; functions 0..18, then exp (19) and log (20).
+constexpr int NFUNC_IDX = CR_NUM_F32 + 2;
+std::atomic<int> g_cfg_variant[2][NFUNC_IDX];
+std::atomic<int> g_cfg_bpc[2][NFUNC_IDX];  // 0: the default
+
+int fidx(int f) { return f < CR_NUM_F32 ? f : (f == CR_EXP ? CR_NUM_F32 : CR_NUM_F32 + 1); }
+int iidx(int impl) { return impl == CR_IMPL_SPLIT_F32 ? 1 : 0; }
+// sincos and the binary64 functions have one kernel shape (variant 0 only)
+int num_variants_of(int f) { return (f == CR_SINCOSF || f >= 64) ? 1 : NVARIANT; }
+
+int eval_cfg(int func_id, int impl, unsigned flags, const void* in, void* out, size_t n,
+             hipStream_t s, int variant, int bpc) {
+  DevStats* st = nullptr;
+  int rc = get_stats(&st);
+  if (rc) return rc;
+  const int g = num_cus() * (bpc > 0 ? bpc : default_bpc());
+  if (func_id < CR_NUM_F32 && impl == CR_IMPL_SPLIT_F32)
+    rc = dispatch_f32_split(func_id, (const float*)in, (float*)out, n, s, flags, st, variant, g);
+  else if (func_id < CR_NUM_F32)
+    rc = dispatch_f32(func_id, (const float*)in, (float*)out, n, s, flags, st, variant, g);
+  else if (func_id == CR_EXP)
+    rc = launch_map_f64<OpExp64>((const double*)in, (double*)out, n, s, flags, st, g);
+  else
+    rc = launch_map_f64<OpLog64>((const double*)in, (double*)out, n, s, flags, st, g);
+  if (rc == CR_OK) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    g_elems[dev] += n;
+  }
+  return rc;
+}
+
+const char* const FUNC_NAMES[NFUNC_IDX] = {
+    "expf", "exp2f", "exp10f", "expm1f", "logf", "log2f", "log10f", "log1pf", "rsqrtf",
+    "sinf", "cosf", "sincosf", "tanf", "asinf", "acosf", "atanf", "sinhf", "coshf", "tanhf",
+    "exp", "log"};
+
+int func_of_idx(int i) { return i < CR_NUM_F32 ? i : (i == CR_NUM_F32 ? CR_EXP : CR_LOG); }
 
 // ------------------------------------------------------------ batch plans
 }  // namespace
@@ -1259,24 +1416,171 @@ int cr_eval_ex(int func_id, int impl, unsigned flags, const void* in, void* out,
   bool same = a == b && nout == n;
   if (!same && a < b + nout * es && b < a + n * es) return CR_E_OVERLAP;
   if (!cr_available(func_id, impl)) return CR_E_IMPL;
-  DevStats* st = nullptr;
-  int rc = get_stats(&st);
+  const int ii = iidx(impl), fi = fidx(func_id);
+  return eval_cfg(func_id, impl, flags, in, out, n, (hipStream_t)stream,
+                  g_cfg_variant[ii][fi].load(), g_cfg_bpc[ii][fi].load());
+}
+
+// ------------------------------------------------------------------ tuning
+int cr_tune_num_variants(void) { return NVARIANT; }
+
+int cr_tune_variant_info(int variant, int* elems_per_thread, int* prefetch, int* table_in_lds) {
+  if (variant < 0 || variant >= NVARIANT) return CR_E_TUNE;
+  if (elems_per_thread) *elems_per_thread = 4 * VARIANTS[variant][0];
+  if (prefetch) *prefetch = VARIANTS[variant][1];
+  if (table_in_lds) *table_in_lds = VARIANTS[variant][2] ? 0 : 1;
+  return CR_OK;
+}
+
+static int tune_check(int func_id, int impl, const cr_tune_cfg* cfg) {
+  if (!func_valid(func_id)) return CR_E_FUNC;
+  if (impl != CR_IMPL_AUTO && impl != CR_IMPL_F64_INTERNAL && impl != CR_IMPL_SPLIT_F32)
+    return CR_E_IMPL;
+  if (!cfg) return CR_E_NULL;
+  if (cfg->variant < 0 || cfg->variant >= num_variants_of(func_id)) return CR_E_TUNE;
+  if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64) return CR_E_TUNE;
+  return CR_OK;
+}
+
+int cr_tune_get(int func_id, int impl, cr_tune_cfg* cfg) {
+  if (!func_valid(func_id)) return CR_E_FUNC;
+  if (impl != CR_IMPL_AUTO && impl != CR_IMPL_F64_INTERNAL && impl != CR_IMPL_SPLIT_F32)
+    return CR_E_IMPL;
+  if (!cfg) return CR_E_NULL;
+  const int ii = iidx(impl), fi = fidx(func_id);
+  cfg->variant = g_cfg_variant[ii][fi].load();
+  int b = g_cfg_bpc[ii][fi].load();
+  cfg->blocks_per_cu = b > 0 ? b : default_bpc();
+  return CR_OK;
+}
+
+int cr_tune_set(int func_id, int impl, const cr_tune_cfg* cfg) {
+  int rc = tune_check(func_id, impl, cfg);
   if (rc) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  if (func_id < CR_NUM_F32 && impl == CR_IMPL_SPLIT_F32)
-    rc = dispatch_f32_split(func_id, (const float*)in, (float*)out, n, s, flags, st);
-  else if (func_id < CR_NUM_F32)
-    rc = dispatch_f32(func_id, (const float*)in, (float*)out, n, s, flags, st);
-  else if (func_id == CR_EXP)
-    rc = launch_map_f64<OpExp64>((const double*)in, (double*)out, n, s, flags, st);
-  else
-    rc = launch_map_f64<OpLog64>((const double*)in, (double*)out, n, s, flags, st);
-  if (rc == CR_OK) {
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    g_elems[dev] += n;
+  const int ii = iidx(impl), fi = fidx(func_id);
+  g_cfg_variant[ii][fi] = cfg->variant;
+  g_cfg_bpc[ii][fi] = cfg->blocks_per_cu;
+  return CR_OK;
+}
+
+int cr_tune_reset(void) {
+  for (int i = 0; i < 2; i++)
+    for (int f = 0; f < NFUNC_IDX; f++) {
+      g_cfg_variant[i][f] = 0;
+      g_cfg_bpc[i][f] = 0;
+    }
+  return CR_OK;
+}
+
+int cr_tune_save(const char* path) {
+  if (!path) return CR_E_NULL;
+  FILE* fp = fopen(path, "w");
+  if (!fp) return CR_E_TUNE;
+  fprintf(fp, "# libcr launch configurations: function implementation variant blocks_per_cu\n");
+  for (int i = 0; i < 2; i++)
+    for (int f = 0; f < NFUNC_IDX; f++) {
+      int b = g_cfg_bpc[i][f].load();
+      fprintf(fp, "%s %s %d %d\n", FUNC_NAMES[f], i ? "split" : "f64", g_cfg_variant[i][f].load(),
+              b > 0 ? b : default_bpc());
+    }
+  int bad = ferror(fp);
+  if (fclose(fp) != 0 || bad) return CR_E_TUNE;
+  return CR_OK;
+}
+
+int cr_tune_load(const char* path) {
+  if (!path) return CR_E_NULL;
+  FILE* fp = fopen(path, "r");
+  if (!fp) return CR_E_TUNE;
+  struct Entry { int impl, func, variant, bpc; };
+  std::vector<Entry> es;
+  char line[512];
+  int rc = CR_OK;
+  while (fgets(line, sizeof line, fp)) {
+    char* p = line;
+    while (*p == ' ' || *p == '\t') p++;
+    if (*p == '#' || *p == '\n' || *p == '\r' || *p == 0) continue;
+    char fname[64], iname[16];
+    int v = -1, b = -1;
+    if (sscanf(p, "%63s %15s %d %d", fname, iname, &v, &b) != 4) {
+      rc = CR_E_TUNE;
+      break;
+    }
+    int f = -1;
+    for (int k = 0; k < NFUNC_IDX; k++)
+      if (!strcmp(fname, FUNC_NAMES[k])) f = func_of_idx(k);
+    int impl = !strcmp(iname, "f64") ? CR_IMPL_F64_INTERNAL
+               : !strcmp(iname, "split") ? CR_IMPL_SPLIT_F32 : -1;
+    cr_tune_cfg c = {v, b};
+    if (f < 0 || impl < 0 || tune_check(f, impl, &c) != CR_OK) {
+      rc = CR_E_TUNE;
+      break;
+    }
+    es.push_back({impl, f, v, b});
   }
-  return rc;
+  fclose(fp);
+  if (rc) return rc;  // nothing applied from a malformed file
+  for (const Entry& e : es) {
+    g_cfg_variant[iidx(e.impl)][fidx(e.func)] = e.variant;
+    g_cfg_bpc[iidx(e.impl)][fidx(e.func)] = e.bpc;
+  }
+  return CR_OK;
+}
+
+int cr_autotune(int func_id, int impl, const void* in, void* out, size_t n, int reps,
+                void* stream, double* best_gelem_s) {
+  if (!func_valid(func_id)) return CR_E_FUNC;
+  if (impl != CR_IMPL_AUTO && impl != CR_IMPL_F64_INTERNAL && impl != CR_IMPL_SPLIT_F32)
+    return CR_E_IMPL;
+  if (n == 0 || !in || !out) return CR_E_NULL;
+  const size_t es = func_id >= 64 ? 8 : 4;
+  const size_t nout = func_id == CR_SINCOSF ? 2 * n : n;
+  if (n > ((size_t)1 << 60)) return CR_E_SIZE;
+  uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+  if ((a % es) || (b % es)) return CR_E_ALIGN;
+  bool same = a == b && nout == n;
+  if (!same && a < b + nout * es && b < a + n * es) return CR_E_OVERLAP;
+  if (!cr_available(func_id, impl)) return CR_E_IMPL;
+  if (reps <= 0) reps = 5;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(e);
+  }
+  static const int BPCS[] = {2, 4, 8, 16, 32};
+  float best_ms = 0.0f;
+  int best_v = 0, best_b = 0, rc = CR_OK;
+  for (int v = 0; v < num_variants_of(func_id) && rc == CR_OK; v++) {
+    for (int bpc : BPCS) {
+      rc = eval_cfg(func_id, impl, 0u, in, out, n, s, v, bpc);  // warm-up
+      if (rc) break;
+      e = hipEventRecord(e0, s);
+      for (int r = 0; r < reps && e == hipSuccess && rc == CR_OK; r++)
+        rc = eval_cfg(func_id, impl, 0u, in, out, n, s, v, bpc);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) rc = hip_fail(e);
+      if (rc) break;
+      if (best_ms == 0.0f || ms < best_ms) {
+        best_ms = ms;
+        best_v = v;
+        best_b = bpc;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  const int ii = iidx(impl), fi = fidx(func_id);
+  g_cfg_variant[ii][fi] = best_v;
+  g_cfg_bpc[ii][fi] = best_b;
+  if (best_gelem_s) *best_gelem_s = best_ms > 0 ? (double)n * reps / (best_ms * 1e-3) / 1e9 : 0.0;
+  return CR_OK;
 }
 
 int cr_available(int func_id, int impl) {
@@ -1462,6 +1766,7 @@ const char* cr_status_str(int status) {
     case CR_E_HIP: return "HIP runtime error";
     case CR_E_NOMEM: return "device allocation failed";
     case CR_E_SIZE: return "size too large";
+    case CR_E_TUNE: return "invalid launch configuration or tuning file";
   }
   return "unknown status";
 }

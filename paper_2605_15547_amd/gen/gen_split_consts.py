@@ -152,6 +152,32 @@ def gen_log():
     emit()
 
 
+def gen_trig():
+    emit("// ---- trigonometric family, binary32-only ----")
+    emit("// sin(j pi/32), cos(j pi/32), j = 0..15: {sin hi, sin lo, cos hi, cos lo}")
+    emit("__device__ __constant__ const float4 STRIG_T[16] = {")
+    for j in range(16):
+        a = mp.pi * j / 32
+        sh, sl = ff(mp.sin(a))
+        ch, cl = ff(mp.cos(a))
+        emit("  {%s, %s, %s, %s}," % (fx(sh), fx(sl), fx(ch), fx(cl)))
+    emit("};")
+    h, l = ff(mp.pi / 32)
+    emit_f("STRIG_PI32_H", h, "pi/32 hi")
+    emit_f("STRIG_PI32_L", l, "pi/32 lo")
+    emit_f("STRIG_PI64", f32(mp.pi / 64, "z"), "pi/64 rounded down")
+    for name, v in (("STRIG_S3", -mp.mpf(1) / 6), ("STRIG_C4", mp.mpf(1) / 24)):
+        h, l = ff(v)
+        emit_f(name + "_H", h)
+        emit_f(name + "_L", l)
+    emit_f("STRIG_S5", f32(mp.mpf(1) / 120), "1/5!")
+    emit_f("STRIG_S7", f32(-mp.mpf(1) / 5040), "-1/7!")
+    emit_f("STRIG_S9", f32(mp.mpf(1) / 362880), "1/9!")
+    emit_f("STRIG_C6", f32(-mp.mpf(1) / 720), "-1/6!")
+    emit_f("STRIG_C8", f32(mp.mpf(1) / 40320), "1/8!")
+    emit()
+
+
 SLOG_S = 112
 
 
@@ -163,6 +189,7 @@ def main():
     emit()
     gen_exp()
     gen_log()
+    gen_trig()
     with open(OUT, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("wrote", OUT)

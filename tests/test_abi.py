@@ -87,3 +87,55 @@ def test_batch_validation(L):
     assert plan.value is None
     assert L.cr_batch_plan_launch(None, None) == -2
     assert L.cr_batch_plan_destroy(None) == 0
+
+
+def test_tuning_table(L, tmp_path):
+    """Launch configurations: defaults, set/get, validation, save/load round
+    trip, and a malformed file applying nothing (host only, no GPU)."""
+    from paper_2605_15547_amd import crmath as C
+    C.tune_reset()
+    vs = C.tune_variants()
+    assert len(vs) == L.cr_tune_num_variants() >= 2
+    assert vs[0] == (8, 1, 1)  # the default: 8 elements per thread, prefetch, LDS tables
+    assert {e for e, _, _ in vs} == {4, 8, 16} and {t for _, _, t in vs} == {0, 1}
+    assert C.tune_get("expf") == (0, 16)
+    C.tune_set("logf", C.IMPL_F64_INTERNAL, 2, 8)
+    assert C.tune_get("logf", C.IMPL_AUTO) == (2, 8)  # AUTO is the binary64-internal table
+    assert C.tune_get("logf", C.IMPL_SPLIT_F32) == (0, 16)
+    for func, impl, v, b in (("expf", 1, len(vs), 16), ("expf", 1, -1, 16), ("expf", 1, 0, 65),
+                             ("sincosf", 1, 1, 16), ("exp", 1, 2, 16)):
+        with pytest.raises(C.CrError) as e:
+            C.tune_set(func, impl, v, b)
+        assert e.value.status == -10
+    with pytest.raises(C.CrError):
+        C.tune_set("expf", 7, 0, 16)
+    p = str(tmp_path / "tune.txt")
+    C.tune_save(p)
+    C.tune_reset()
+    assert C.tune_get("logf") == (0, 16)
+    C.tune_load(p)
+    assert C.tune_get("logf") == (2, 8)
+    bad = tmp_path / "bad.txt"
+    bad.write_text("# header\nexpf f64 3 4\nnosuchf f64 0 16\n")
+    with pytest.raises(C.CrError):
+        C.tune_load(str(bad))
+    assert C.tune_get("expf") == (0, 16)  # nothing applied
+    for text in ("expf f64 0\n", "expf f32 0 16\n", "sincosf split 2 16\n", "log f64 0 99\n"):
+        bad.write_text(text)
+        with pytest.raises(C.CrError):
+            C.tune_load(str(bad))
+    with pytest.raises(C.CrError):
+        C.tune_load(str(tmp_path / "missing.txt"))
+    ok = tmp_path / "ok.txt"
+    ok.write_text("  # comment\n\nexpf split 6 4\nexp f64 0 2\n")
+    C.tune_load(str(ok))
+    assert C.tune_get("expf", C.IMPL_SPLIT_F32) == (6, 4) and C.tune_get("exp") == (0, 2)
+    C.tune_reset()
+    # the autotuner validates its arguments before touching the GPU
+    vp = ctypes.c_void_p
+    at = L.cr_autotune
+    assert at(0, 0, None, vp(0x2000), 8, 1, None, None) == -2
+    assert at(99, 0, vp(0x1000), vp(0x2000), 8, 1, None, None) == -1
+    assert at(0, 5, vp(0x1000), vp(0x2000), 8, 1, None, None) == -5
+    assert at(0, 0, vp(0x1001), vp(0x2000), 8, 1, None, None) == -4
+    assert at(0, 0, vp(0x1000), vp(0x1004), 8, 1, None, None) == -3
