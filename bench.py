@@ -74,7 +74,7 @@ def bench_family(torch, crmath, inputs, funcs, n, impl, steps, warmup, stream):
     return {"elems_per_function": n, "per_func": res}
 
 
-def bench_batch(torch, crmath, inputs, steps, warmup, stream):
+def bench_batch(torch, crmath, inputs, steps, warmup, stream, impl=1):
     """The ragged batch: 4096 requests of mixed binary32 functions, lengths
     log-uniform in [1, 2^20], evaluated by one graph launch per step."""
     funcs, lens, seeds = inputs.batch_requests()
@@ -86,7 +86,7 @@ def bench_batch(torch, crmath, inputs, steps, warmup, stream):
         xt = torch.from_numpy(x).cuda()
         ot = torch.empty(2 * n if f == "sincosf" else n, dtype=torch.float32, device="cuda")
         bufs.append((xt, ot))
-        reqs.append((f, xt.data_ptr(), ot.data_ptr(), n))
+        reqs.append((f, xt.data_ptr(), ot.data_ptr(), n, impl))
         total += n
         nbytes += bytes_per_elem(f) * n
     t0 = time.perf_counter()
@@ -254,11 +254,13 @@ def main():
         extra["binary64_exp_log"] = bench_family(
             torch, crmath, inputs, ["exp", "log"], 1 << 24, 0, a.steps, a.warmup, stream)
         extra["ragged_batch"] = bench_batch(torch, crmath, inputs, a.steps, a.warmup, stream)
+        extra["ragged_batch_split_f32"] = bench_batch(torch, crmath, inputs, a.steps, a.warmup,
+                                                      stream, impl=2)
         # the binary32-only (float-float) implementation beside the binary64-internal one
         extra["exp_log_family_split_f32"] = bench_family(
             torch, crmath, inputs, FAMILY, n, 2, a.steps, a.warmup, stream)
-        extra["trig_split_f32"] = bench_family(
-            torch, crmath, inputs, ["sinf", "cosf", "sincosf", "tanf"], n, 2, a.steps, a.warmup,
+        extra["trig_hyperbolic_family_split_f32"] = bench_family(
+            torch, crmath, inputs, TRIG, n, 2, a.steps, a.warmup,
             stream)
 
     cpu = None

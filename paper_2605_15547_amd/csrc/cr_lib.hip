@@ -28,6 +28,9 @@
 #include "cr_split_exp.h"
 #include "cr_split_log.h"
 #include "cr_split_trig.h"
+#include "cr_split_rsqrt.h"
+#include "cr_split_atan.h"
+#include "cr_split_hyp.h"
 
 using namespace cr;
 
@@ -137,6 +140,45 @@ struct SinCosSplit {
   }
   static __device__ __forceinline__ AccResult2 accurate(float x, const Tab& t) {
     return sincos_accurate(x, t.acc);
+  }
+};
+
+struct OpSRsqrt {
+  using Tab = NoTab;
+  static constexpr int qcheck = QCHECK;
+  static __device__ __forceinline__ void load(Tab&, int) {}
+  static __device__ __forceinline__ float fast(float x, const Tab&, bool& ok) {
+    return srsqrt_fast(x, ok);
+  }
+  static __device__ __forceinline__ AccResult accurate(float x, const Tab&) {
+    bool ok;
+    return {srsqrt_fast(x, ok), 1};
+  }
+};
+
+template <int KIND>
+struct OpSAtan {
+  using Tab = SAtanTab;
+  static constexpr int qcheck = 1;  // more lanes fail: look at the queue every tile
+  static __device__ __forceinline__ void load(Tab& t, int tid) { satan_tab_load(t, tid); }
+  static __device__ __forceinline__ float fast(float x, const Tab& t, bool& ok) {
+    return satan_fast<KIND>(x, t, ok);
+  }
+  static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
+    return atan_accurate<KIND>(x, t.acc);
+  }
+};
+
+template <int KIND>
+struct OpSHyp {
+  using Tab = SHypTab;
+  static constexpr int qcheck = 1;  // more lanes fail: look at the queue every tile
+  static __device__ __forceinline__ void load(Tab& t, int tid) { shyp_tab_load(t, tid); }
+  static __device__ __forceinline__ float fast(float x, const Tab& t, bool& ok) {
+    return shyp_fast<KIND>(x, t, ok);
+  }
+  static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
+    return hyp_accurate<KIND>(x, t.acc);
   }
 };
 
@@ -745,7 +787,9 @@ struct BReq {
   long long n;
   int func;
   int aligned;  // in and out (and the cos block for sincosf) are 16-byte aligned
+  int key;      // func + BSPLIT for the binary32-only implementation
 };
+constexpr int BSPLIT = 32;
 struct BTile {
   int req;
   int count;
@@ -758,6 +802,11 @@ union BatchTab {
   TrigTab t;
   AtanTab a;
   NoTab z;
+  SExpTab se;
+  SLogTab sl;
+  STrigTab st;
+  SAtanTab sa;
+  SHypTab sh;
 };
 
 struct BDeferred {
@@ -767,8 +816,8 @@ struct BDeferred {
   float x[QCAP];
 };
 
-__device__ __forceinline__ void batch_tab_load(BatchTab& t, int func, int tid) {
-  switch (func) {
+__device__ __forceinline__ void batch_tab_load(BatchTab& t, int key, int tid) {
+  switch (key) {
     case CR_EXPF: case CR_EXP2F: case CR_EXP10F: case CR_EXPM1F:
     case CR_SINHF: case CR_COSHF: case CR_TANHF:
       exp_tab_load(t.e, tid);
@@ -778,6 +827,22 @@ __device__ __forceinline__ void batch_tab_load(BatchTab& t, int func, int tid) {
     case CR_LOG10F: log_tab_load<LOGK_10>(t.l, tid); break;
     case CR_SINF: case CR_COSF: case CR_SINCOSF: case CR_TANF: trig_tab_load(t.t, tid); break;
     case CR_ASINF: case CR_ACOSF: case CR_ATANF: atan_tab_load(t.a, tid); break;
+    case BSPLIT + CR_EXPF: case BSPLIT + CR_EXP2F: case BSPLIT + CR_EXP10F:
+      sexp_tab_load<EXPK_E>(t.se, tid);
+      break;
+    case BSPLIT + CR_EXPM1F: sexp_tab_load<EXPK_EM1>(t.se, tid); break;
+    case BSPLIT + CR_LOGF: case BSPLIT + CR_LOG1PF: slog_tab_load<LOGK_E>(t.sl, tid); break;
+    case BSPLIT + CR_LOG2F: slog_tab_load<LOGK_2>(t.sl, tid); break;
+    case BSPLIT + CR_LOG10F: slog_tab_load<LOGK_10>(t.sl, tid); break;
+    case BSPLIT + CR_SINF: case BSPLIT + CR_COSF: case BSPLIT + CR_SINCOSF: case BSPLIT + CR_TANF:
+      strig_tab_load(t.st, tid);
+      break;
+    case BSPLIT + CR_ASINF: case BSPLIT + CR_ACOSF: case BSPLIT + CR_ATANF:
+      satan_tab_load(t.sa, tid);
+      break;
+    case BSPLIT + CR_SINHF: case BSPLIT + CR_COSHF: case BSPLIT + CR_TANHF:
+      shyp_tab_load(t.sh, tid);
+      break;
     default: break;
   }
 }
@@ -846,7 +911,8 @@ __device__ __noinline__ void batch_tile(BReq R, BTile T, const typename Op::Tab&
   }
 }
 
-__device__ __noinline__ void batch_tile_sincos(BReq R, BTile T, const TrigTab& tab,
+template <class SC>
+__device__ __noinline__ void batch_tile_sincos(BReq R, BTile T, const typename SC::Tab& tab,
                                                BDeferred& q, bool force, DevStats* st) {
   const float* in = reinterpret_cast<const float*>(R.in) + T.start;
   float* os = reinterpret_cast<float*>(R.out) + T.start;
@@ -856,7 +922,7 @@ __device__ __noinline__ void batch_tile_sincos(BReq R, BTile T, const TrigTab& t
   for (int i = threadIdx.x; i < cnt; i += BLOCK) {
     bool ok;
     float x = in[i], c;
-    float sv = sincos_fast(x, tab, c, ok);
+    float sv = SC::fast(x, tab, c, ok);
     if (!ok || force) {
       unsigned pos = atomicAdd(&q.n, 1u);
       if (pos < QCAP) {
@@ -864,7 +930,7 @@ __device__ __noinline__ void batch_tile_sincos(BReq R, BTile T, const TrigTab& t
         q.idx[pos] = base + i;
         q.x[pos] = x;
       } else {
-        AccResult2 a = sincos_accurate(x, tab);
+        AccResult2 a = SC::accurate(x, tab);
         sv = a.s;
         c = a.c;
         atomicAdd(&q.lanes, 1u);
@@ -893,12 +959,29 @@ __device__ __forceinline__ void batch_flush_op(BDeferred& q, unsigned n, const t
   }
 }
 
+template <class SC>
+__device__ __forceinline__ void batch_flush_sincos(BDeferred& q, unsigned n,
+                                                   const typename SC::Tab& tab, const BReq* reqs,
+                                                   DevStats* st) {
+  for (unsigned k = threadIdx.x; k < n; k += BLOCK) {
+    AccResult2 a = SC::accurate(q.x[k], tab);
+    const BReq& R = reqs[q.req[k]];
+    float* out = reinterpret_cast<float*>(R.out);
+    out[q.idx[k]] = a.s;
+    out[R.n + q.idx[k]] = a.c;
+    if (!a.ok) {
+      atomicAdd(&q.esc, 1u);
+      note_escape(st, (long long)q.idx[k]);
+    }
+  }
+}
+
 // Run the accurate path on the queued elements (all of function func), then
 // empty the queue.  Called by all threads of the workgroup.
-__device__ __noinline__ void batch_flush(BDeferred& q, const BatchTab& tab, int func,
+__device__ __noinline__ void batch_flush(BDeferred& q, const BatchTab& tab, int key,
                                          const BReq* reqs, DevStats* st) {
   unsigned n = q.n < QCAP ? q.n : QCAP;
-  switch (func) {
+  switch (key) {
     case CR_EXPF: batch_flush_op<OpExp<EXPK_E>>(q, n, tab.e, reqs, st); break;
     case CR_EXP2F: batch_flush_op<OpExp<EXPK_2>>(q, n, tab.e, reqs, st); break;
     case CR_EXP10F: batch_flush_op<OpExp<EXPK_10>>(q, n, tab.e, reqs, st); break;
@@ -911,25 +994,32 @@ __device__ __noinline__ void batch_flush(BDeferred& q, const BatchTab& tab, int 
     case CR_SINF: batch_flush_op<OpTrig<TRIGK_SIN>>(q, n, tab.t, reqs, st); break;
     case CR_COSF: batch_flush_op<OpTrig<TRIGK_COS>>(q, n, tab.t, reqs, st); break;
     case CR_TANF: batch_flush_op<OpTrig<TRIGK_TAN>>(q, n, tab.t, reqs, st); break;
-    case CR_SINCOSF:
-      for (unsigned k = threadIdx.x; k < n; k += BLOCK) {
-        AccResult2 a = sincos_accurate(q.x[k], tab.t);
-        const BReq& R = reqs[q.req[k]];
-        float* out = reinterpret_cast<float*>(R.out);
-        out[q.idx[k]] = a.s;
-        out[R.n + q.idx[k]] = a.c;
-        if (!a.ok) {
-          atomicAdd(&q.esc, 1u);
-          note_escape(st, (long long)q.idx[k]);
-        }
-      }
-      break;
+    case CR_SINCOSF: batch_flush_sincos<SinCosF64>(q, n, tab.t, reqs, st); break;
     case CR_ASINF: batch_flush_op<OpAtan<ATANK_ASIN>>(q, n, tab.a, reqs, st); break;
     case CR_ACOSF: batch_flush_op<OpAtan<ATANK_ACOS>>(q, n, tab.a, reqs, st); break;
     case CR_ATANF: batch_flush_op<OpAtan<ATANK_ATAN>>(q, n, tab.a, reqs, st); break;
     case CR_SINHF: batch_flush_op<OpHyp<HYPK_SINH>>(q, n, tab.e, reqs, st); break;
     case CR_COSHF: batch_flush_op<OpHyp<HYPK_COSH>>(q, n, tab.e, reqs, st); break;
     case CR_TANHF: batch_flush_op<OpHyp<HYPK_TANH>>(q, n, tab.e, reqs, st); break;
+    case BSPLIT + CR_EXPF: batch_flush_op<OpSExp<EXPK_E>>(q, n, tab.se, reqs, st); break;
+    case BSPLIT + CR_EXP2F: batch_flush_op<OpSExp<EXPK_2>>(q, n, tab.se, reqs, st); break;
+    case BSPLIT + CR_EXP10F: batch_flush_op<OpSExp<EXPK_10>>(q, n, tab.se, reqs, st); break;
+    case BSPLIT + CR_EXPM1F: batch_flush_op<OpSExp<EXPK_EM1>>(q, n, tab.se, reqs, st); break;
+    case BSPLIT + CR_LOGF: batch_flush_op<OpSLog<LOGK_E>>(q, n, tab.sl, reqs, st); break;
+    case BSPLIT + CR_LOG2F: batch_flush_op<OpSLog<LOGK_2>>(q, n, tab.sl, reqs, st); break;
+    case BSPLIT + CR_LOG10F: batch_flush_op<OpSLog<LOGK_10>>(q, n, tab.sl, reqs, st); break;
+    case BSPLIT + CR_LOG1PF: batch_flush_op<OpSLog<LOGK_1P>>(q, n, tab.sl, reqs, st); break;
+    case BSPLIT + CR_RSQRTF: batch_flush_op<OpSRsqrt>(q, n, tab.z, reqs, st); break;
+    case BSPLIT + CR_SINF: batch_flush_op<OpSTrig<TRIGK_SIN>>(q, n, tab.st, reqs, st); break;
+    case BSPLIT + CR_COSF: batch_flush_op<OpSTrig<TRIGK_COS>>(q, n, tab.st, reqs, st); break;
+    case BSPLIT + CR_TANF: batch_flush_op<OpSTrig<TRIGK_TAN>>(q, n, tab.st, reqs, st); break;
+    case BSPLIT + CR_SINCOSF: batch_flush_sincos<SinCosSplit>(q, n, tab.st, reqs, st); break;
+    case BSPLIT + CR_ASINF: batch_flush_op<OpSAtan<ATANK_ASIN>>(q, n, tab.sa, reqs, st); break;
+    case BSPLIT + CR_ACOSF: batch_flush_op<OpSAtan<ATANK_ACOS>>(q, n, tab.sa, reqs, st); break;
+    case BSPLIT + CR_ATANF: batch_flush_op<OpSAtan<ATANK_ATAN>>(q, n, tab.sa, reqs, st); break;
+    case BSPLIT + CR_SINHF: batch_flush_op<OpSHyp<HYPK_SINH>>(q, n, tab.sh, reqs, st); break;
+    case BSPLIT + CR_COSHF: batch_flush_op<OpSHyp<HYPK_COSH>>(q, n, tab.sh, reqs, st); break;
+    case BSPLIT + CR_TANHF: batch_flush_op<OpSHyp<HYPK_TANH>>(q, n, tab.sh, reqs, st); break;
     default: break;
   }
   if (threadIdx.x == 0) {
@@ -957,11 +1047,11 @@ __global__ void __launch_bounds__(BLOCK)
   for (long long t = t0; t < t1; t++, iter++) {
     const BTile T = tiles[t];
     const BReq R = reqs[T.req];
-    if (R.func != cur) {
+    if (R.key != cur) {
       __syncthreads();
       if (cur >= 0 && q.n) batch_flush(q, tab, cur, reqs, st);
-      batch_tab_load(tab, R.func, threadIdx.x);
-      cur = R.func;
+      batch_tab_load(tab, R.key, threadIdx.x);
+      cur = R.key;
       __syncthreads();
     }
     switch (cur) {
@@ -976,7 +1066,7 @@ __global__ void __launch_bounds__(BLOCK)
       case CR_RSQRTF: batch_tile<OpRsqrt>(R, T, tab.z, q, force, st); break;
       case CR_SINF: batch_tile<OpTrig<TRIGK_SIN>>(R, T, tab.t, q, force, st); break;
       case CR_COSF: batch_tile<OpTrig<TRIGK_COS>>(R, T, tab.t, q, force, st); break;
-      case CR_SINCOSF: batch_tile_sincos(R, T, tab.t, q, force, st); break;
+      case CR_SINCOSF: batch_tile_sincos<SinCosF64>(R, T, tab.t, q, force, st); break;
       case CR_TANF: batch_tile<OpTrig<TRIGK_TAN>>(R, T, tab.t, q, force, st); break;
       case CR_ASINF: batch_tile<OpAtan<ATANK_ASIN>>(R, T, tab.a, q, force, st); break;
       case CR_ACOSF: batch_tile<OpAtan<ATANK_ACOS>>(R, T, tab.a, q, force, st); break;
@@ -984,9 +1074,31 @@ __global__ void __launch_bounds__(BLOCK)
       case CR_SINHF: batch_tile<OpHyp<HYPK_SINH>>(R, T, tab.e, q, force, st); break;
       case CR_COSHF: batch_tile<OpHyp<HYPK_COSH>>(R, T, tab.e, q, force, st); break;
       case CR_TANHF: batch_tile<OpHyp<HYPK_TANH>>(R, T, tab.e, q, force, st); break;
+      case BSPLIT + CR_EXPF: batch_tile<OpSExp<EXPK_E>>(R, T, tab.se, q, force, st); break;
+      case BSPLIT + CR_EXP2F: batch_tile<OpSExp<EXPK_2>>(R, T, tab.se, q, force, st); break;
+      case BSPLIT + CR_EXP10F: batch_tile<OpSExp<EXPK_10>>(R, T, tab.se, q, force, st); break;
+      case BSPLIT + CR_EXPM1F: batch_tile<OpSExp<EXPK_EM1>>(R, T, tab.se, q, force, st); break;
+      case BSPLIT + CR_LOGF: batch_tile<OpSLog<LOGK_E>>(R, T, tab.sl, q, force, st); break;
+      case BSPLIT + CR_LOG2F: batch_tile<OpSLog<LOGK_2>>(R, T, tab.sl, q, force, st); break;
+      case BSPLIT + CR_LOG10F: batch_tile<OpSLog<LOGK_10>>(R, T, tab.sl, q, force, st); break;
+      case BSPLIT + CR_LOG1PF: batch_tile<OpSLog<LOGK_1P>>(R, T, tab.sl, q, force, st); break;
+      case BSPLIT + CR_RSQRTF: batch_tile<OpSRsqrt>(R, T, tab.z, q, force, st); break;
+      case BSPLIT + CR_SINF: batch_tile<OpSTrig<TRIGK_SIN>>(R, T, tab.st, q, force, st); break;
+      case BSPLIT + CR_COSF: batch_tile<OpSTrig<TRIGK_COS>>(R, T, tab.st, q, force, st); break;
+      case BSPLIT + CR_SINCOSF:
+        batch_tile_sincos<SinCosSplit>(R, T, tab.st, q, force, st);
+        break;
+      case BSPLIT + CR_TANF: batch_tile<OpSTrig<TRIGK_TAN>>(R, T, tab.st, q, force, st); break;
+      case BSPLIT + CR_ASINF: batch_tile<OpSAtan<ATANK_ASIN>>(R, T, tab.sa, q, force, st); break;
+      case BSPLIT + CR_ACOSF: batch_tile<OpSAtan<ATANK_ACOS>>(R, T, tab.sa, q, force, st); break;
+      case BSPLIT + CR_ATANF: batch_tile<OpSAtan<ATANK_ATAN>>(R, T, tab.sa, q, force, st); break;
+      case BSPLIT + CR_SINHF: batch_tile<OpSHyp<HYPK_SINH>>(R, T, tab.sh, q, force, st); break;
+      case BSPLIT + CR_COSHF: batch_tile<OpSHyp<HYPK_COSH>>(R, T, tab.sh, q, force, st); break;
+      case BSPLIT + CR_TANHF: batch_tile<OpSHyp<HYPK_TANH>>(R, T, tab.sh, q, force, st); break;
       default: break;
     }
-    if (iter % QCHECK == QCHECK - 1) {
+    // split tiles fail the rounding test more often: look at the queue every tile
+    if (cur >= BSPLIT || iter % QCHECK == QCHECK - 1) {
       __syncthreads();
       const unsigned nq = q.n;
       __syncthreads();
@@ -1229,7 +1341,7 @@ int launch_map_f64(const double* in, double* out, size_t n, hipStream_t s, unsig
 bool func_valid(int f) { return (f >= 0 && f < CR_NUM_F32) || f == CR_EXP || f == CR_LOG; }
 bool func_built(int f) { return (f >= CR_EXPF && f <= CR_TANHF) || f == CR_EXP || f == CR_LOG; }
 // functions with a binary32-only (split) implementation
-bool split_built(int f) { return (f >= CR_EXPF && f <= CR_LOG1PF) || (f >= CR_SINF && f <= CR_TANF); }
+bool split_built(int f) { return f >= CR_EXPF && f <= CR_TANHF; }
 
 int dispatch_f32_split(int f, const float* in, float* out, size_t n, hipStream_t s,
                        unsigned flags, DevStats* st, int v, int g) {
@@ -1242,10 +1354,17 @@ int dispatch_f32_split(int f, const float* in, float* out, size_t n, hipStream_t
     case CR_LOG2F: return launch_variant<OpSLog<LOGK_2>>(in, out, n, s, flags, st, v, g);
     case CR_LOG10F: return launch_variant<OpSLog<LOGK_10>>(in, out, n, s, flags, st, v, g);
     case CR_LOG1PF: return launch_variant<OpSLog<LOGK_1P>>(in, out, n, s, flags, st, v, g);
+    case CR_RSQRTF: return launch_variant<OpSRsqrt>(in, out, n, s, flags, st, v, g);
     case CR_SINF: return launch_variant<OpSTrig<TRIGK_SIN>>(in, out, n, s, flags, st, v, g);
     case CR_COSF: return launch_variant<OpSTrig<TRIGK_COS>>(in, out, n, s, flags, st, v, g);
     case CR_TANF: return launch_variant<OpSTrig<TRIGK_TAN>>(in, out, n, s, flags, st, v, g);
     case CR_SINCOSF: return launch_sincos<SinCosSplit>(in, out, n, s, flags, st, g);
+    case CR_ASINF: return launch_variant<OpSAtan<ATANK_ASIN>>(in, out, n, s, flags, st, v, g);
+    case CR_ACOSF: return launch_variant<OpSAtan<ATANK_ACOS>>(in, out, n, s, flags, st, v, g);
+    case CR_ATANF: return launch_variant<OpSAtan<ATANK_ATAN>>(in, out, n, s, flags, st, v, g);
+    case CR_SINHF: return launch_variant<OpSHyp<HYPK_SINH>>(in, out, n, s, flags, st, v, g);
+    case CR_COSHF: return launch_variant<OpSHyp<HYPK_COSH>>(in, out, n, s, flags, st, v, g);
+    case CR_TANHF: return launch_variant<OpSHyp<HYPK_TANH>>(in, out, n, s, flags, st, v, g);
   }
   return CR_E_IMPL;
 }
@@ -1350,7 +1469,8 @@ int build_tables(const cr_request* reqs, int32_t num, std::vector<BReq>& hr,
   for (int i = 0; i < num; i++) {
     const cr_request& r = reqs[i];
     if (r.func_id < 0 || r.func_id >= CR_NUM_F32) return CR_E_FUNC;
-    if (r.impl != CR_IMPL_AUTO && r.impl != CR_IMPL_F64_INTERNAL) return CR_E_IMPL;
+    if (r.impl != CR_IMPL_AUTO && r.impl != CR_IMPL_F64_INTERNAL && r.impl != CR_IMPL_SPLIT_F32)
+      return CR_E_IMPL;
     if (r.n < 0 || r.n >= ((int64_t)1 << 31)) return CR_E_SIZE;
     if (r.n == 0) continue;
     if (!r.in || !r.out) return CR_E_NULL;
@@ -1361,10 +1481,13 @@ int build_tables(const cr_request* reqs, int32_t num, std::vector<BReq>& hr,
     if (!same && a < b + nout * 4 && b < a + (size_t)r.n * 4) return CR_E_OVERLAP;
     if (!cr_available(r.func_id, r.impl)) return CR_E_IMPL;
   }
-  // order requests by function so that tiles of one function are adjacent
+  // order requests by (implementation, function) so that tiles sharing tables
+  // are adjacent
+  auto key = [&](int i) {
+    return reqs[i].func_id + (reqs[i].impl == CR_IMPL_SPLIT_F32 ? BSPLIT : 0);
+  };
   for (int i = 0; i < num; i++) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int x, int y) { return reqs[x].func_id < reqs[y].func_id; });
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(x) < key(y); });
   for (int oi = 0; oi < num; oi++) {
     const cr_request& r = reqs[order[oi]];
     if (r.n == 0) continue;
@@ -1373,6 +1496,7 @@ int build_tables(const cr_request* reqs, int32_t num, std::vector<BReq>& hr,
     q.out = r.out;
     q.n = r.n;
     q.func = r.func_id;
+    q.key = key(order[oi]);
     uintptr_t a = (uintptr_t)r.in, b = (uintptr_t)r.out;
     uintptr_t c = b + 4 * (uintptr_t)r.n;
     q.aligned = ((a | b) & 15) == 0 && (r.func_id != CR_SINCOSF || (c & 15) == 0);

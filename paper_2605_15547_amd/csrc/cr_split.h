@@ -45,6 +45,18 @@ __device__ __forceinline__ float pow2f_i(int e) {
                    : __uint_as_float(1u << (e + 149));
 }
 
+// a / b for float-float a, b (b != 0): quotient estimate from the hardware
+// reciprocal, float-float residual, two corrections (relative error ~2^-46)
+__device__ __forceinline__ ff ff_div(ff a, ff b) {
+  float ic = __builtin_amdgcn_rcpf(b.hi);
+  float q1 = a.hi * ic;
+  ff p = ff_two_prod(q1, b.hi);
+  float rem = ((a.hi - p.hi) - p.lo) + fmaf(-q1, b.lo, a.lo);
+  float q2 = rem * ic;
+  q2 = fmaf(fmaf(-q2, b.hi, rem), ic, q2);
+  return ff_fast_two_sum(q1, q2);
+}
+
 // Final rounding of a split result.  The exact value lies within err of
 // h + l (h, l binary32, |l| small against h; err >= 0 covers every error,
 // including the two roundings below).  RN_32 is monotone, so when

@@ -77,6 +77,55 @@ __device__ __forceinline__ ff sexp_reduce(float x, float& kf) {
   }
 }
 
+// k = 256 m + 16 j1 + j0 with balanced digits j1, j0 in [-8, 7]
+struct SExpDigits {
+  int m, i1, i0;  // i1 = j1 + 8, i0 = j0 + 8: table indices
+};
+
+__device__ __forceinline__ SExpDigits sexp_digits(float kf) {
+  int k = (int)kf;
+  SExpDigits d;
+  d.m = (k + 136) >> 8;  // floor: k - 256 m in [-136, 119]
+  int rem = k - (d.m << 8);
+  int j1 = (rem + 8) >> 4;  // [-8, 7]
+  d.i1 = j1 + 8;
+  d.i0 = rem - (j1 << 4) + 8;
+  return d;
+}
+
+// q = e^r - 1 = r + r^2/2 + r^3/6 + r^4/24 for a normalised float-float r
+__device__ __forceinline__ ff sexp_q(ff r) {
+  ff sq = ff_two_prod(r.hi, r.hi);
+  float t3 = sq.hi * r.hi * fmaf(r.hi, SEXP_INV24, SEXP_INV6);
+  ff qh = ff_fast_two_sum(r.hi, 0.5f * sq.hi);
+  float ql = qh.lo + (r.lo + (fmaf(r.hi, r.lo, 0.5f * sq.lo) + t3));
+  return ff_fast_two_sum(qh.hi, ql);
+}
+
+// y = T1 T2 (1 + q) (not normalised: |lo| may reach a few ulps of hi)
+__device__ __forceinline__ ff sexp_T(float2 A, float2 B, ff q) {
+  ff P = ff_two_prod(A.x, B.x);
+  float Pl = fmaf(A.x, B.y, fmaf(A.y, B.x, P.lo));
+  ff PQ = ff_two_prod(P.hi, q.hi);
+  ff Y = ff_fast_two_sum(P.hi, PQ.hi);
+  return {Y.hi, Y.lo + (Pl + (PQ.lo + fmaf(P.hi, q.lo, Pl * q.hi)))};
+}
+
+// W = D12 + q (1 + D12), D12 = D1 + D2 + D1 D2 = T1 T2 - 1 (tables of 2^j - 1)
+__device__ __forceinline__ ff sexp_W(float2 A, float2 B, ff q) {
+  // |D1| >= 0.043 > |D2| unless D1 = 0
+  ff S = ff_fast_two_sum(A.x, B.x);
+  ff P = ff_two_prod(A.x, B.x);
+  ff U = ff_fast_two_sum(S.hi, P.hi);
+  float ul = U.lo + (S.lo + ((A.y + B.y) + (P.lo + fmaf(A.x, B.y, A.y * B.x))));
+  ff D = ff_fast_two_sum(U.hi, ul);
+  // |D12| >= 0.0027 > |q| unless D12 = 0
+  ff QD = ff_two_prod(q.hi, D.hi);
+  ff V = ff_fast_two_sum(D.hi, q.hi);
+  ff V2 = ff_fast_two_sum(V.hi, QD.hi);
+  return {V2.hi, (V.lo + V2.lo) + ((D.lo + q.lo) + (QD.lo + fmaf(q.hi, D.lo, q.lo * D.hi)))};
+}
+
 template <int K>
 __device__ __forceinline__ float sexp_fast(float xf, const SExpTab& tb, bool& ok) {
   // clamp: the clamp values over- or underflow by far (expm1: -20 gives -1)
@@ -87,58 +136,34 @@ __device__ __forceinline__ float sexp_fast(float xf, const SExpTab& tb, bool& ok
   float x = fminf(fmaxf(xf, lo_lim), hi_lim);
   float kf;
   ff r = sexp_reduce<K>(x, kf);
-  int k = (int)kf;
-  int m = (k + 136) >> 8;  // floor: k - 256 m in [-136, 119]
-  int rem = k - (m << 8);
-  int j1 = (rem + 8) >> 4;  // [-8, 7]
-  int j0 = rem - (j1 << 4); // [-8, 7]
-  float2 A = tb.t1[j1 + 8], B = tb.t2[j0 + 8];
-
-  // q = e^r - 1 = r + r^2/2 + r^3/6 + r^4/24
-  ff sq = ff_two_prod(r.hi, r.hi);
-  float t3 = sq.hi * r.hi * fmaf(r.hi, SEXP_INV24, SEXP_INV6);
-  ff qh = ff_fast_two_sum(r.hi, 0.5f * sq.hi);
-  float ql = qh.lo + (r.lo + (fmaf(r.hi, r.lo, 0.5f * sq.lo) + t3));
-  ff q = ff_fast_two_sum(qh.hi, ql);
+  SExpDigits dg = sexp_digits(kf);
+  const int m = dg.m;
+  float2 A = tb.t1[dg.i1], B = tb.t2[dg.i0];
+  ff q = sexp_q(r);
 
   float res;
   if (K != EXPK_EM1) {
-    // y = T1 T2 (1 + q)
-    ff P = ff_two_prod(A.x, B.x);
-    float Pl = fmaf(A.x, B.y, fmaf(A.y, B.x, P.lo));
-    ff PQ = ff_two_prod(P.hi, q.hi);
-    ff Y = ff_fast_two_sum(P.hi, PQ.hi);
-    float yl = Y.lo + (Pl + (PQ.lo + fmaf(P.hi, q.lo, Pl * q.hi)));
+    ff Y = sexp_T(A, B, q);
     bool okn, okq;
-    res = ldexpf(round_split(Y.hi, yl, 0x1p-44f, okn), m);
+    res = ldexpf(round_split(Y.hi, Y.lo, 0x1p-44f, okn), m);
     // results below 2^-125: round y 2^(m+149) to an integer (m >= -217)
     float sc = pow2f_i(m + 149 < 23 ? m + 149 : 23);
-    float rq = round_split_q(Y.hi * sc, yl * sc, fmaf(0x1p-44f, sc, 0x1p-22f), okq);
+    float rq = round_split_q(Y.hi * sc, Y.lo * sc, fmaf(0x1p-44f, sc, 0x1p-22f), okq);
     ok = okn;
     if (m <= -126) {
       res = rq;
       ok = okq;
     }
   } else {
-    // D12 = D1 + D2 + D1 D2  (|D1| >= 0.043 > |D2| unless D1 = 0)
-    ff S = ff_fast_two_sum(A.x, B.x);
-    ff P = ff_two_prod(A.x, B.x);
-    ff U = ff_fast_two_sum(S.hi, P.hi);
-    float ul = U.lo + (S.lo + ((A.y + B.y) + (P.lo + fmaf(A.x, B.y, A.y * B.x))));
-    ff D = ff_fast_two_sum(U.hi, ul);
-    // W = D12 + q + q D12  (|D12| >= 0.0027 > |q| unless D12 = 0)
-    ff QD = ff_two_prod(q.hi, D.hi);
-    ff V = ff_fast_two_sum(D.hi, q.hi);
-    ff V2 = ff_fast_two_sum(V.hi, QD.hi);
-    float wl = (V.lo + V2.lo) + ((D.lo + q.lo) + (QD.lo + fmaf(q.hi, D.lo, q.lo * D.hi)));
+    ff W = sexp_W(A, B, q);
     // u = (1 + W) - 2^-m; m = 0: u = W
-    ff O = ff_fast_two_sum(1.0f, V2.hi);
+    ff O = ff_fast_two_sum(1.0f, W.hi);
     ff Uu = ff_two_sum(O.hi, -pow2f_i(-m));  // m in [-29, 130]
-    float uh = Uu.hi, ulo = Uu.lo + (O.lo + wl), err = 0x1p-45f;
+    float uh = Uu.hi, ulo = Uu.lo + (O.lo + W.lo), err = 0x1p-45f;
     if (m == 0) {
-      uh = V2.hi;
-      ulo = wl;
-      err = fabsf(V2.hi) * 0x1p-42f;
+      uh = W.hi;
+      ulo = W.lo;
+      err = fabsf(W.hi) * 0x1p-42f;
     }
     res = ldexpf(round_split(uh, ulo, err, ok), m);
   }

@@ -178,6 +178,25 @@ def gen_trig():
     emit()
 
 
+def gen_atan():
+    emit("// ---- inverse trigonometric family, binary32-only ----")
+    emit("// {atan(j/16) hi, lo, (pi/2 - atan(j/16)) hi, lo}, j = 0..15")
+    emit("__device__ __constant__ const float4 SATAN_T[16] = {")
+    for j in range(16):
+        a = mp.atan(mp.mpf(j) / 16)
+        h, l = ff(a)
+        h2, l2 = ff(mp.pi / 2 - a)
+        emit("  {%s, %s, %s, %s}," % (fx(h), fx(l), fx(h2), fx(l2)))
+    emit("};")
+    for name, v in (("SATAN_PI", mp.pi), ("SATAN_THIRD", mp.mpf(1) / 3)):
+        h, l = ff(v)
+        emit_f(name + "_H", h)
+        emit_f(name + "_L", l)
+    for k in (5, 7, 9, 11, 13):
+        emit_f("SATAN_P%d" % k, f32(mp.mpf((-1) ** ((k - 1) // 2)) / k), "(-1)^((k-1)/2)/k")
+    emit()
+
+
 SLOG_S = 112
 
 
@@ -190,6 +209,7 @@ def main():
     gen_exp()
     gen_log()
     gen_trig()
+    gen_atan()
     with open(OUT, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("wrote", OUT)

@@ -43,9 +43,9 @@ def make_requests(num, seed, max_log2, unaligned=False, extra=()):
     return items
 
 
-def req_list(items):
+def req_list(items, impl_of=lambda k: crmath.IMPL_AUTO):
     return [(it["func"], it["xin"].data_ptr() + 4 * it["oi"], it["out"].data_ptr() + 4 * it["oo"],
-             it["n"]) for it in items]
+             it["n"], impl_of(k)) for k, it in enumerate(items)]
 
 
 def check(items, oracle, what):
@@ -127,5 +127,58 @@ def test_batch_full_size_sampled(oracle):
             g = np.stack([got[:n][idx], got[n:][idx]])
         else:
             g = got[idx]
+        assert np.array_equal(g.view(np.uint32), np.asarray(ref).view(np.uint32)), f
+    plan.destroy()
+
+
+def test_batch_mixed_implementations(oracle):
+    """Requests alternating between the binary64-internal and the binary32-only
+    implementation in one plan (replayed twice, the second time with every
+    element forced through the accurate path in a second plan)."""
+    _need_gpu()
+    items = make_requests(240, 5400, 13, unaligned=True, extra=[("sincosf", 3001), ("expf", 1)])
+    impl_of = lambda k: crmath.IMPL_SPLIT_F32 if k % 2 else crmath.IMPL_F64_INTERNAL
+    crmath.stats_reset()
+    plan = crmath.BatchPlan(req_list(items, impl_of))
+    for rep in range(2):
+        for it in items:
+            it["out"].fill_(-3.0)
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        check(items, oracle, "mixed replay %d" % rep)
+    plan.destroy()
+    assert crmath.stats_read()["escapes"] == 0
+    plan = crmath.BatchPlan(req_list(items, impl_of), flags=crmath.FLAG_FORCE_FALLBACK)
+    plan.launch()
+    torch.cuda.synchronize()
+    check(items, oracle, "mixed forced")
+    plan.destroy()
+
+
+def test_batch_full_size_split_sampled(oracle):
+    """The full ragged workload with every request on the binary32-only
+    implementation; a seeded sample of each request is compared."""
+    _need_gpu()
+    funcs, lens, seeds = inputs.batch_requests()
+    xs, outs, reqs = [], [], []
+    for f, n, sd in zip(funcs, lens, seeds):
+        n = int(n)
+        x = inputs.workload_f32(f, n, seed=int(sd))
+        xt = torch.from_numpy(x).cuda()
+        ot = torch.empty(2 * n if f == "sincosf" else n, dtype=torch.float32, device="cuda")
+        xs.append((f, x, xt))
+        outs.append(ot)
+        reqs.append((f, xt.data_ptr(), ot.data_ptr(), n, crmath.IMPL_SPLIT_F32))
+    plan = crmath.BatchPlan(reqs)
+    plan.launch()
+    torch.cuda.synchronize()
+    st = inputs.Stream(778)
+    for (f, x, _), ot in zip(xs, outs):
+        n = x.size
+        idx = st.below(min(n, 16), n)
+        got = ot.cpu().numpy()
+        ref = oracle.evaluate(f, x[idx])
+        g = np.stack([got[:n][idx], got[n:][idx]]) if f == "sincosf" else got[idx]
         assert np.array_equal(g.view(np.uint32), np.asarray(ref).view(np.uint32)), f
     plan.destroy()

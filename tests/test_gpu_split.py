@@ -115,3 +115,30 @@ def test_split_exhaustive_fast_path_matches_accurate_path(func):
     st = crmath.stats_read()
     assert total_bad == 0, (func, total_bad, first)
     assert st["escapes"] == 0, st
+
+
+def test_split_rsqrtf_exhaustive_matches_binary64_decision():
+    """rsqrtf has no accurate path: both implementations decide the rounding
+    exactly (binary64 midpoint residual vs integer comparison); they must agree
+    on every binary32 encoding."""
+    _need("rsqrtf")
+    sp = crmath._stream_ptr(None)
+    total_bad, first = 0, None
+    for c in range(1 << 32 >> 28):
+        xi = torch.arange(c * CHUNK, (c + 1) * CHUNK, dtype=torch.int64, device="cuda")
+        x = xi.to(torch.int32).view(torch.float32)
+        del xi
+        a = torch.empty_like(x)
+        b = torch.empty_like(x)
+        crmath.eval_ptr("rsqrtf", x.data_ptr(), a.data_ptr(), x.numel(), SPLIT, 0, sp)
+        crmath.eval_ptr("rsqrtf", x.data_ptr(), b.data_ptr(), x.numel(),
+                        crmath.IMPL_F64_INTERNAL, 0, sp)
+        bad = a.view(torch.int32) != b.view(torch.int32)
+        nb = int(bad.sum().item())
+        if nb and first is None:
+            i = int(torch.nonzero(bad)[0].item())
+            first = hex(c * CHUNK + i)
+        total_bad += nb
+        del a, b, bad, x
+    torch.cuda.synchronize()
+    assert total_bad == 0, (total_bad, first)
