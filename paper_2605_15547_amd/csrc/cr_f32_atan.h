@@ -58,24 +58,15 @@ __device__ __forceinline__ void atan_ratio_fast(double Y0, double X0, const Atan
 // test uses 16.
 constexpr int ATAN_LOG2E = 4;
 
+// Branch-free: res is always written (meaningful only when true is returned).
 __device__ __forceinline__ bool atan_special(float xf, int kind, float& res) {
-  if (xf != xf) {
-    res = bits_f32(f32_bits(xf) | 0x00400000u);
-    return true;
-  }
-  if (kind != ATANK_ATAN && fabsf(xf) > 1.0f) {
-    res = bits_f32(0x7fc00000u);
-    return true;
-  }
-  if (kind != ATANK_ACOS && xf == 0.0f) {
-    res = xf;  // atan(+-0) = asin(+-0) = +-0
-    return true;
-  }
-  if (kind == ATANK_ACOS && xf == 1.0f) {
-    res = 0.0f;
-    return true;
-  }
-  return false;
+  const bool nan = xf != xf;
+  const bool dom = kind != ATANK_ATAN && fabsf(xf) > 1.0f;
+  const bool zero = kind != ATANK_ACOS && xf == 0.0f;  // atan(+-0) = asin(+-0) = +-0
+  const bool one = kind == ATANK_ACOS && xf == 1.0f;
+  float v = zero ? xf : (one ? 0.0f : bits_f32(0x7fc00000u));
+  res = nan ? bits_f32(f32_bits(xf) | 0x00400000u) : v;
+  return nan | dom | zero | one;
 }
 
 template <int KIND>

@@ -131,21 +131,16 @@ __device__ __forceinline__ ExpSetup<K> exp_setup(float xf, const ExpTab& tb) {
 // Inputs whose result is fixed without evaluation: NaN (returned quieted),
 // exp2f(-150) = 2^-150, the one exact midpoint (ties to even give +0), and
 // expm1(+-0) = +-0.
+// Branch-free: res is always written (meaningful only when true is returned),
+// so the compiler keeps the main computation outside any branch.
 template <int K>
 __device__ __forceinline__ bool exp_special(float xf, float& res) {
-  if (xf != xf) {
-    res = bits_f32(f32_bits(xf) | 0x00400000u);
-    return true;
-  }
-  if (K == EXPK_2 && xf == -150.0f) {
-    res = 0.0f;
-    return true;
-  }
-  if (K == EXPK_EM1 && xf == 0.0f) {
-    res = xf;
-    return true;
-  }
-  return false;
+  const bool nan = xf != xf;
+  const bool tie = K == EXPK_2 && xf == -150.0f;
+  const bool zero = K == EXPK_EM1 && xf == 0.0f;
+  float v = zero ? xf : 0.0f;
+  res = nan ? bits_f32(f32_bits(xf) | 0x00400000u) : v;
+  return nan | tie | zero;
 }
 
 // Fast path: binary64 evaluation and the rounding test.  ok = false means the
@@ -167,7 +162,11 @@ __device__ __forceinline__ float exp_fast(float xf, const ExpTab& tb, bool& ok) 
     yh = scale_exp(S.T.x + fma(S.T.x, q, S.T.y), S.m);  // |m| <= 217: stays normal
   }
   float res = round_f32_fast<ExpErr<K>::LOG2E>(yh, ok);
-  if (exp_special<K>(xf, res)) ok = true;
+  float sp;
+  if (exp_special<K>(xf, sp)) {
+    res = sp;
+    ok = true;
+  }
   return res;
 }
 

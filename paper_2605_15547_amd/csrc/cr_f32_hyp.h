@@ -39,16 +39,12 @@ __device__ __forceinline__ double exp_core_fast(float af, double a, const ExpTab
 // <= 3; the test uses 32 ulps.
 constexpr int HYP_LOG2E = 5;
 
+// Branch-free: res is always written (meaningful only when true is returned).
 __device__ __forceinline__ bool hyp_special(float xf, int kind, float& res) {
-  if (xf != xf) {
-    res = bits_f32(f32_bits(xf) | 0x00400000u);
-    return true;
-  }
-  if (kind != HYPK_COSH && xf == 0.0f) {
-    res = xf;
-    return true;
-  }
-  return false;
+  const bool nan = xf != xf;
+  const bool zero = kind != HYPK_COSH && xf == 0.0f;
+  res = nan ? bits_f32(f32_bits(xf) | 0x00400000u) : xf;
+  return nan | zero;
 }
 
 template <int KIND>

@@ -135,25 +135,18 @@ __device__ __forceinline__ LogSetup log_setup(float xf, const LogTab& tb) {
 }
 
 // NaN (quieted), u <= 0 (-inf at 0, NaN below), u = +inf, log1p(+-0) = +-0.
+// Branch-free: res is always written (meaningful only when true is returned).
 template <int K>
 __device__ __forceinline__ bool log_special(float xf, double u, float& res) {
-  if (xf != xf) {
-    res = bits_f32(f32_bits(xf) | 0x00400000u);
-    return true;
-  }
-  if (K == LOGK_1P && xf == 0.0f) {
-    res = xf;
-    return true;
-  }
-  if (!(u > 0.0)) {
-    res = u == 0.0 ? -INFINITY : bits_f32(0x7fc00000u);
-    return true;
-  }
-  if (u == INFINITY) {
-    res = INFINITY;
-    return true;
-  }
-  return false;
+  const bool nan = xf != xf;
+  const bool zero1p = K == LOGK_1P && xf == 0.0f;
+  const bool nonpos = !(u > 0.0);
+  const bool inf = u == INFINITY;
+  float v = inf ? INFINITY : bits_f32(0x7fc00000u);
+  v = u == 0.0 ? -INFINITY : v;
+  v = zero1p ? xf : v;
+  res = nan ? bits_f32(f32_bits(xf) | 0x00400000u) : v;
+  return nan | zero1p | nonpos | inf;
 }
 
 template <int K>
@@ -166,7 +159,11 @@ __device__ __forceinline__ float log_fast(float xf, const LogTab& tb, bool& ok) 
   double inner = fma(t, Q, A.lo + fma(ed, log_C_lo<K>(), S.L.y));
   double yh = A.hi + fma(log_K<K>(), t, inner);
   float res = round_f32_fast<LOG_LOG2E>(yh, ok);
-  if (log_special<K>(xf, S.u, res)) ok = true;
+  float sp;
+  if (log_special<K>(xf, S.u, sp)) {
+    res = sp;
+    ok = true;
+  }
   return res;
 }
 

@@ -19,24 +19,16 @@ struct NoTab {
   int unused;
 };
 
+// Branch-free: res is always written (meaningful only when true is returned).
 __device__ __forceinline__ bool rsqrt_special(float xf, float& res) {
-  if (xf != xf) {
-    res = bits_f32(f32_bits(xf) | 0x00400000u);
-    return true;
-  }
-  if (xf == 0.0f) {  // rsqrt(+-0) = +-inf
-    res = bits_f32((f32_bits(xf) & 0x80000000u) | 0x7f800000u);
-    return true;
-  }
-  if (xf < 0.0f) {
-    res = bits_f32(0x7fc00000u);
-    return true;
-  }
-  if (xf == INFINITY) {
-    res = 0.0f;
-    return true;
-  }
-  return false;
+  const bool nan = xf != xf;
+  const bool zero = xf == 0.0f;  // rsqrt(+-0) = +-inf
+  const bool neg = xf < 0.0f;
+  const bool inf = xf == INFINITY;
+  float v = inf ? 0.0f : bits_f32(0x7fc00000u);
+  v = zero ? bits_f32((f32_bits(xf) & 0x80000000u) | 0x7f800000u) : v;
+  res = nan ? bits_f32(f32_bits(xf) | 0x00400000u) : v;
+  return nan | zero | neg | inf;
 }
 
 __device__ __forceinline__ float rsqrt_eval(float xf) {
@@ -59,9 +51,10 @@ __device__ __forceinline__ float rsqrt_eval(float xf) {
 
 __device__ __forceinline__ float rsqrt_fast(float xf, bool& ok) {
   ok = true;
-  float res;
-  if (rsqrt_special(xf, res)) return res;
-  return rsqrt_eval(xf);
+  float sp;
+  const bool s = rsqrt_special(xf, sp);
+  const float r = rsqrt_eval(s ? 1.0f : xf);  // special inputs: any valid operand
+  return s ? sp : r;
 }
 
 }  // namespace cr

@@ -105,20 +105,14 @@ __device__ __forceinline__ SinCosTheta theta_of(int q, const TrigTab& tb) {
   return r;
 }
 
+// Branch-free: res is always written (meaningful only when true is returned).
 __device__ __forceinline__ bool trig_special(float xf, float& res, int kind) {
-  if (xf != xf) {
-    res = bits_f32(f32_bits(xf) | 0x00400000u);
-    return true;
-  }
-  if ((f32_bits(xf) & 0x7fffffffu) == 0x7f800000u) {
-    res = bits_f32(0x7fc00000u);
-    return true;
-  }
-  if (xf == 0.0f) {
-    res = kind == TRIGK_COS ? 1.0f : xf;  // sin, tan keep the sign of zero
-    return true;
-  }
-  return false;
+  const bool nan = xf != xf;
+  const bool inf = (f32_bits(xf) & 0x7fffffffu) == 0x7f800000u;
+  const bool zero = xf == 0.0f;
+  float v = zero ? (kind == TRIGK_COS ? 1.0f : xf) : bits_f32(0x7fc00000u);  // sin, tan keep -0
+  res = nan ? bits_f32(f32_bits(xf) | 0x00400000u) : v;
+  return nan | inf | zero;
 }
 
 // Fast path: binary64 sin and cos of x with absolute error bounds.

@@ -45,16 +45,11 @@ __device__ __forceinline__ void log64_tab_load(Log64Tab& t, int tid) {
 }
 
 // ------------------------------------------------------------------- exp
+// Branch-free: res is always written (meaningful only when true is returned).
 __device__ __forceinline__ bool exp64_special(double x, double& res) {
-  if (x != x) {
-    res = __longlong_as_double(__double_as_longlong(x) | 0x0008000000000000ll);
-    return true;
-  }
-  if (x == 0.0) {
-    res = 1.0;
-    return true;
-  }
-  return false;
+  const bool nan = x != x;
+  res = nan ? __longlong_as_double(__double_as_longlong(x) | 0x0008000000000000ll) : 1.0;
+  return nan | (x == 0.0);
 }
 
 // main-path error: q within 2^-71, tables 2^-104, products and sum 2^-104:
@@ -143,28 +138,16 @@ __device__ __noinline__ AccResultD exp64_accurate(double x, const Exp64Tab& tb) 
 }
 
 // ------------------------------------------------------------------- log
+// Branch-free: res is always written (meaningful only when true is returned).
 __device__ __forceinline__ bool log64_special(double x, double& res) {
-  if (x != x) {
-    res = __longlong_as_double(__double_as_longlong(x) | 0x0008000000000000ll);
-    return true;
-  }
-  if (x == 0.0) {
-    res = -INFINITY;
-    return true;
-  }
-  if (x < 0.0) {
-    res = __longlong_as_double(0x7ff8000000000000ll);
-    return true;
-  }
-  if (x == INFINITY) {
-    res = INFINITY;
-    return true;
-  }
-  if (x == 1.0) {
-    res = 0.0;
-    return true;
-  }
-  return false;
+  const bool nan = x != x;
+  const bool nonpos = x <= 0.0;
+  const bool inf = x == INFINITY;
+  const bool one = x == 1.0;
+  double v = one ? 0.0 : (inf ? INFINITY : __longlong_as_double(0x7ff8000000000000ll));
+  v = x == 0.0 ? -INFINITY : v;
+  res = nan ? __longlong_as_double(__double_as_longlong(x) | 0x0008000000000000ll) : v;
+  return nan | nonpos | inf | one;
 }
 
 struct Log64Setup {

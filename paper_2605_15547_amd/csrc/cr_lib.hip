@@ -373,7 +373,7 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
     for (int u = 0; u < U; u++) {
       long long i = base + (long long)u * BLOCK;
-      if (i < n4) nxt[u] = ld_stream(in + i);
+      nxt[u] = i < n4 ? ld_stream(in + i) : make_float4(1.0f, 1.0f, 1.0f, 1.0f);
     }
   }
   int iter = 0;
@@ -387,7 +387,7 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
       for (int u = 0; u < U; u++) {
         long long i = base + (long long)u * BLOCK;
-        if (i < n4) v[u] = ld_stream(in + i);
+        v[u] = i < n4 ? ld_stream(in + i) : make_float4(1.0f, 1.0f, 1.0f, 1.0f);
       }
     }
     if (PF) {
@@ -395,20 +395,36 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
       for (int u = 0; u < U; u++) {
         long long i = nb + (long long)u * BLOCK;
-        if (i < n4) nxt[u] = ld_stream(in + i);
+        nxt[u] = i < n4 ? ld_stream(in + i) : make_float4(1.0f, 1.0f, 1.0f, 1.0f);
       }
     }
+    // Evaluate every element of the tile first -- straight-line code with no
+    // branch between elements, so the scheduler can interleave their
+    // dependency chains -- then queue the elements that failed the test.
+    // Slots past the end hold stale values: evaluated, never stored or queued.
+    float xin[4 * U];
+    unsigned fail = 0;
 #pragma unroll
     for (int u = 0; u < U; u++) {
-      long long i = base + (long long)u * BLOCK;
-      if (i < n4) {
+      const bool live = base + (long long)u * BLOCK < n4;
+      float* e = reinterpret_cast<float*>(&v[u]);
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        bool ok;
+        xin[4 * u + c] = e[c];
+        e[c] = Op::fast(e[c], tab, ok);
+        fail |= (unsigned)(live && (!ok || force)) << (4 * u + c);
+      }
+    }
+    if (fail) {
+#pragma unroll
+      for (int u = 0; u < U; u++) {
         float* e = reinterpret_cast<float*>(&v[u]);
 #pragma unroll
         for (int c = 0; c < 4; c++) {
-          bool ok;
-          float x = e[c];
-          e[c] = Op::fast(x, tab, ok);
-          if (!ok || force) {
+          if (fail & (1u << (4 * u + c))) {
+            const long long i = base + (long long)u * BLOCK;
+            const float x = xin[4 * u + c];
             unsigned pos = atomicAdd(&q.n, 1u);
             if (pos < QCAP) {
               q.idx[pos] = (unsigned)(4 * i + c);

@@ -45,30 +45,18 @@ __device__ __forceinline__ void slog_tab_load(SLogTab& t, int tid) {
 }
 
 // NaN (quieted), zero and negative arguments, +inf, log1p(+-0) = +-0
+// Branch-free: res is always written (meaningful only when true is returned).
 template <int K>
 __device__ __forceinline__ bool slog_special(float xf, float& res) {
-  if (xf != xf) {
-    res = bits_f32(f32_bits(xf) | 0x00400000u);
-    return true;
-  }
-  if (K == LOGK_1P) {
-    if (xf == 0.0f) {
-      res = xf;
-      return true;
-    }
-    if (xf <= -1.0f) {
-      res = xf == -1.0f ? -INFINITY : bits_f32(0x7fc00000u);
-      return true;
-    }
-  } else if (xf <= 0.0f) {
-    res = xf == 0.0f ? -INFINITY : bits_f32(0x7fc00000u);
-    return true;
-  }
-  if (xf == INFINITY) {
-    res = INFINITY;
-    return true;
-  }
-  return false;
+  const bool nan = xf != xf;
+  const float lim = K == LOGK_1P ? -1.0f : 0.0f;  // log1p(-1) = log(+-0) = -inf
+  const bool zero1p = K == LOGK_1P && xf == 0.0f;
+  const bool dom = xf <= lim;
+  const bool inf = xf == INFINITY;
+  float v = inf ? INFINITY : (xf == lim ? -INFINITY : bits_f32(0x7fc00000u));
+  v = zero1p ? xf : v;
+  res = nan ? bits_f32(f32_bits(xf) | 0x00400000u) : v;
+  return nan | zero1p | dom | inf;
 }
 
 template <int K>

@@ -46,9 +46,10 @@ __device__ __forceinline__ float srsqrt_eval(float xf) {
 
 __device__ __forceinline__ float srsqrt_fast(float xf, bool& ok) {
   ok = true;
-  float res;
-  if (rsqrt_special(xf, res)) return res;
-  return srsqrt_eval(xf);
+  float sp;
+  const bool s = rsqrt_special(xf, sp);
+  const float r = srsqrt_eval(s ? 1.0f : xf);  // special inputs: any valid operand
+  return s ? sp : r;
 }
 
 }  // namespace cr
