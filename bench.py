@@ -40,11 +40,20 @@ def bytes_per_elem(func):
     return 16 if func in ("exp", "log") else (12 if func == "sincosf" else 8)
 
 
-def bench_family(torch, crmath, inputs, funcs, n, impl, steps, warmup, stream):
+def settle(fn, seconds, torch):
+    """Untimed launches for `seconds` so the clocks settle under this load."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        fn()
+        torch.cuda.synchronize()
+
+
+def bench_family(torch, crmath, inputs, funcs, n, impl, steps, warmup, stream, settle_s=0.5):
     """Gelem/s and HBM fraction per function (inputs resident in HBM), plus the
     accurate-path share, for a family workload of n elements per function."""
     sp = crmath._stream_ptr(stream)
     res = {}
+    bufs = {}
     for f in funcs:
         if not crmath.available(f, impl):
             res[f] = None
@@ -52,14 +61,22 @@ def bench_family(torch, crmath, inputs, funcs, n, impl, steps, warmup, stream):
         x = inputs.workload_f64(f, n) if f in ("exp", "log") else inputs.workload_f32(f, n)
         xt = torch.from_numpy(x).cuda()
         ot = torch.empty(2 * n if f == "sincosf" else n, dtype=xt.dtype, device="cuda")
+        bufs[f] = (xt, ot)
+
+    def launch(f):
+        xt, ot = bufs[f]
+        crmath.eval_ptr(f, xt.data_ptr(), ot.data_ptr(), n, impl, 0, sp)
+
+    settle(lambda: [launch(f) for f in bufs], settle_s, torch)
+    for f in bufs:
         for _ in range(warmup):
-            crmath.eval_ptr(f, xt.data_ptr(), ot.data_ptr(), n, impl, 0, sp)
+            launch(f)
         torch.cuda.synchronize()
         crmath.stats_reset()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(steps):
-            crmath.eval_ptr(f, xt.data_ptr(), ot.data_ptr(), n, impl, 0, sp)
+            launch(f)
         e1.record(stream)
         torch.cuda.synchronize()
         st = crmath.stats_read()
@@ -68,10 +85,12 @@ def bench_family(torch, crmath, inputs, funcs, n, impl, steps, warmup, stream):
         res[f] = {"ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
                   "gb_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                   "fallback_lane_rate": st["fallback_lanes"] / (n * steps),
-                  "escapes": st["escapes"]}
-        del xt, ot
+                  "escapes": st["escapes"], "launch": list(crmath.tune_get(f, impl))}
+    del bufs
+    torch.cuda.empty_cache()
     log("bench: family", funcs[0], "...", {k: v and v["gelem_s"] for k, v in res.items()})
-    return {"elems_per_function": n, "per_func": res}
+    return {"elems_per_function": n, "impl": "split_f32" if impl == 2 else "f64_internal",
+            "per_func": res}
 
 
 def bench_batch(torch, crmath, inputs, steps, warmup, stream, impl=1):
@@ -92,6 +111,7 @@ def bench_batch(torch, crmath, inputs, steps, warmup, stream, impl=1):
     t0 = time.perf_counter()
     plan = crmath.BatchPlan(reqs)
     create_s = time.perf_counter() - t0
+    settle(lambda: plan.launch(stream), 0.3, torch)
     for _ in range(warmup):
         plan.launch(stream)
     torch.cuda.synchronize()
@@ -104,7 +124,8 @@ def bench_batch(torch, crmath, inputs, steps, warmup, stream, impl=1):
     ms = e0.elapsed_time(e1) / steps
     plan.destroy()
     gbs = nbytes / (ms * 1e-3) / 1e9
-    r = {"requests": len(reqs), "elements": total, "ms": round(ms, 3),
+    r = {"impl": "split_f32" if impl == 2 else "f64_internal",
+         "requests": len(reqs), "elements": total, "ms": round(ms, 3),
          "gelem_s": round(total / (ms * 1e-3) / 1e9, 2), "gb_s": round(gbs, 1),
          "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "plan_create_s": round(create_s, 3)}
     log("bench: batch", r)
@@ -148,6 +169,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=26, help="log2 of elements per function")
     ap.add_argument("--impl", type=int, default=1)
+    ap.add_argument("--settle", type=float, default=1.0,
+                    help="seconds of untimed steps before the warm-up (clock settling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2605_15547_amd", "tuning",
@@ -195,6 +218,13 @@ def main():
     def run(f):
         crmath.eval_ptr(f, xs[f].data_ptr(), outs[f].data_ptr(), n, a.impl, 0, sp)
 
+    # let the clocks settle under this load before the warm-up steps (the first
+    # ~100 ms of work run at lower clocks)
+    t_settle = time.perf_counter()
+    while time.perf_counter() - t_settle < a.settle:
+        for f in funcs:
+            run(f)
+        torch.cuda.synchronize()
     for _ in range(a.warmup):
         for f in funcs:
             run(f)

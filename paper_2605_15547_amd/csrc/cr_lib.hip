@@ -1681,7 +1681,7 @@ int cr_autotune(int func_id, int impl, const void* in, void* out, size_t n, int 
   bool same = a == b && nout == n;
   if (!same && a < b + nout * es && b < a + n * es) return CR_E_OVERLAP;
   if (!cr_available(func_id, impl)) return CR_E_IMPL;
-  if (reps <= 0) reps = 5;
+  if (reps <= 0) reps = 10;
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
@@ -1691,26 +1691,47 @@ int cr_autotune(int func_id, int impl, const void* in, void* out, size_t n, int 
     return hip_fail(e);
   }
   static const int BPCS[] = {2, 4, 8, 16, 32};
-  float best_ms = 0.0f;
-  int best_v = 0, best_b = 0, rc = CR_OK;
-  for (int v = 0; v < num_variants_of(func_id) && rc == CR_OK; v++) {
-    for (int bpc : BPCS) {
-      rc = eval_cfg(func_id, impl, 0u, in, out, n, s, v, bpc);  // warm-up
-      if (rc) break;
-      e = hipEventRecord(e0, s);
-      for (int r = 0; r < reps && e == hipSuccess && rc == CR_OK; r++)
-        rc = eval_cfg(func_id, impl, 0u, in, out, n, s, v, bpc);
-      if (e == hipSuccess) e = hipEventRecord(e1, s);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
+  constexpr int NB = sizeof(BPCS) / sizeof(BPCS[0]);
+  const int nv = num_variants_of(func_id);
+  // time reps launches of one configuration (after one untimed launch)
+  auto time_cfg = [&](int v, int bpc, float& ms) -> int {
+    int r0 = eval_cfg(func_id, impl, 0u, in, out, n, s, v, bpc);
+    if (r0) return r0;
+    hipError_t he = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && he == hipSuccess && r0 == CR_OK; r++)
+      r0 = eval_cfg(func_id, impl, 0u, in, out, n, s, v, bpc);
+    if (r0) return r0;
+    if (he == hipSuccess) he = hipEventRecord(e1, s);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    return he == hipSuccess ? CR_OK : hip_fail(he);
+  };
+  // Let the clocks settle under this load (about 100 ms of it) before
+  // timing: the first milliseconds of work run at lower clocks and would
+  // favour whichever configuration is timed last.
+  int rc = CR_OK;
+  for (float busy = 0.0f; busy < 100.0f && rc == CR_OK;) {
+    float ms = 0.0f;
+    rc = time_cfg(0, 0, ms);
+    busy += ms > 0.0f ? ms : 100.0f;
+  }
+  // two passes over the space, in opposite orders; the minimum counts
+  std::vector<float> best_of(nv * NB, 0.0f);
+  for (int pass = 0; pass < 2 && rc == CR_OK; pass++) {
+    for (int c = 0; c < nv * NB && rc == CR_OK; c++) {
+      const int idx = pass ? nv * NB - 1 - c : c;
       float ms = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) rc = hip_fail(e);
-      if (rc) break;
-      if (best_ms == 0.0f || ms < best_ms) {
-        best_ms = ms;
-        best_v = v;
-        best_b = bpc;
-      }
+      rc = time_cfg(idx / NB, BPCS[idx % NB], ms);
+      if (rc == CR_OK && (best_of[idx] == 0.0f || ms < best_of[idx])) best_of[idx] = ms;
+    }
+  }
+  float best_ms = 0.0f;
+  int best_v = 0, best_b = 0;
+  for (int idx = 0; idx < nv * NB && rc == CR_OK; idx++) {
+    if (best_ms == 0.0f || best_of[idx] < best_ms) {
+      best_ms = best_of[idx];
+      best_v = idx / NB;
+      best_b = BPCS[idx % NB];
     }
   }
   (void)hipEventDestroy(e0);
