@@ -97,8 +97,8 @@ int cr_eval_ex(int func_id, int impl, unsigned flags, const void *in, void *out,
 int cr_available(int func_id, int impl);
 
 /* ------------------------------------------------------------------ batches
- * Many requests of mixed function and uneven length evaluated by ONE
- * persistent kernel launch, captured once in a HIP graph (the batched form of
+ * Many requests of mixed function and uneven length evaluated by ONE graph
+ * launch (captured once, replayed on every launch; the batched form of
  * the elementwise map; the paper's SIMD functions are called on vectors of
  * arbitrary length, Sec. III-A).  Requests follow the conventions above
  * (device pointers, element alignment, sincosf planar within its own output,
@@ -127,7 +127,10 @@ typedef struct cr_batch_plan cr_batch_plan; /* opaque, owned by the library */
  * CR_E_HIP. */
 int cr_batch_plan_create(const cr_request *reqs, int32_t num, unsigned flags,
                          cr_batch_plan **plan);
-/* Launch the plan's graph on the stream (asynchronous, stream-ordered). */
+/* Launch the plan's graph on the stream (asynchronous, stream-ordered).  The
+ * graph holds one persistent kernel per (implementation, function) present,
+ * run back to back, each over its own contiguous range of 2048-element tiles
+ * (requests are sorted by implementation and function when the plan is made). */
 int cr_batch_plan_launch(cr_batch_plan *plan, void *stream);
 /* Release the plan (synchronises with its last launch first). */
 int cr_batch_plan_destroy(cr_batch_plan *plan);

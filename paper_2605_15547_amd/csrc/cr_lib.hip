@@ -812,56 +812,12 @@ struct BTile {
   long long start;
 };
 
-union BatchTab {
-  ExpTab e;
-  LogTab l;
-  TrigTab t;
-  AtanTab a;
-  NoTab z;
-  SExpTab se;
-  SLogTab sl;
-  STrigTab st;
-  SAtanTab sa;
-  SHypTab sh;
-};
-
 struct BDeferred {
   unsigned n, lanes, waves, esc;
   unsigned req[QCAP];
   unsigned idx[QCAP];
   float x[QCAP];
 };
-
-__device__ __forceinline__ void batch_tab_load(BatchTab& t, int key, int tid) {
-  switch (key) {
-    case CR_EXPF: case CR_EXP2F: case CR_EXP10F: case CR_EXPM1F:
-    case CR_SINHF: case CR_COSHF: case CR_TANHF:
-      exp_tab_load(t.e, tid);
-      break;
-    case CR_LOGF: case CR_LOG1PF: log_tab_load<LOGK_E>(t.l, tid); break;
-    case CR_LOG2F: log_tab_load<LOGK_2>(t.l, tid); break;
-    case CR_LOG10F: log_tab_load<LOGK_10>(t.l, tid); break;
-    case CR_SINF: case CR_COSF: case CR_SINCOSF: case CR_TANF: trig_tab_load(t.t, tid); break;
-    case CR_ASINF: case CR_ACOSF: case CR_ATANF: atan_tab_load(t.a, tid); break;
-    case BSPLIT + CR_EXPF: case BSPLIT + CR_EXP2F: case BSPLIT + CR_EXP10F:
-      sexp_tab_load<EXPK_E>(t.se, tid);
-      break;
-    case BSPLIT + CR_EXPM1F: sexp_tab_load<EXPK_EM1>(t.se, tid); break;
-    case BSPLIT + CR_LOGF: case BSPLIT + CR_LOG1PF: slog_tab_load<LOGK_E>(t.sl, tid); break;
-    case BSPLIT + CR_LOG2F: slog_tab_load<LOGK_2>(t.sl, tid); break;
-    case BSPLIT + CR_LOG10F: slog_tab_load<LOGK_10>(t.sl, tid); break;
-    case BSPLIT + CR_SINF: case BSPLIT + CR_COSF: case BSPLIT + CR_SINCOSF: case BSPLIT + CR_TANF:
-      strig_tab_load(t.st, tid);
-      break;
-    case BSPLIT + CR_ASINF: case BSPLIT + CR_ACOSF: case BSPLIT + CR_ATANF:
-      satan_tab_load(t.sa, tid);
-      break;
-    case BSPLIT + CR_SINHF: case BSPLIT + CR_COSHF: case BSPLIT + CR_TANHF:
-      shyp_tab_load(t.sh, tid);
-      break;
-    default: break;
-  }
-}
 
 template <class Op>
 __device__ __forceinline__ void batch_enqueue(BDeferred& q, const typename Op::Tab& tab,
@@ -884,7 +840,7 @@ __device__ __forceinline__ void batch_enqueue(BDeferred& q, const typename Op::T
 }
 
 template <class Op>
-__device__ __noinline__ void batch_tile(BReq R, BTile T, const typename Op::Tab& tab,
+__device__ __forceinline__ void batch_tile(BReq R, BTile T, const typename Op::Tab& tab,
                                         BDeferred& q, bool force, DevStats* st) {
   const float* in = reinterpret_cast<const float*>(R.in) + T.start;
   float* out = reinterpret_cast<float*>(R.out) + T.start;
@@ -928,7 +884,7 @@ __device__ __noinline__ void batch_tile(BReq R, BTile T, const typename Op::Tab&
 }
 
 template <class SC>
-__device__ __noinline__ void batch_tile_sincos(BReq R, BTile T, const typename SC::Tab& tab,
+__device__ __forceinline__ void batch_tile_sincos(BReq R, BTile T, const typename SC::Tab& tab,
                                                BDeferred& q, bool force, DevStats* st) {
   const float* in = reinterpret_cast<const float*>(R.in) + T.start;
   float* os = reinterpret_cast<float*>(R.out) + T.start;
@@ -992,52 +948,13 @@ __device__ __forceinline__ void batch_flush_sincos(BDeferred& q, unsigned n,
   }
 }
 
-// Run the accurate path on the queued elements (all of function func), then
-// empty the queue.  Called by all threads of the workgroup.
-__device__ __noinline__ void batch_flush(BDeferred& q, const BatchTab& tab, int key,
-                                         const BReq* reqs, DevStats* st) {
+// Run the accurate path on the queued elements, then empty the queue.  Called
+// by all threads of the workgroup.
+template <class Op>
+__device__ __noinline__ void batch_flush_one(BDeferred& q, const typename Op::Tab& tab,
+                                             const BReq* reqs, DevStats* st) {
   unsigned n = q.n < QCAP ? q.n : QCAP;
-  switch (key) {
-    case CR_EXPF: batch_flush_op<OpExp<EXPK_E>>(q, n, tab.e, reqs, st); break;
-    case CR_EXP2F: batch_flush_op<OpExp<EXPK_2>>(q, n, tab.e, reqs, st); break;
-    case CR_EXP10F: batch_flush_op<OpExp<EXPK_10>>(q, n, tab.e, reqs, st); break;
-    case CR_EXPM1F: batch_flush_op<OpExp<EXPK_EM1>>(q, n, tab.e, reqs, st); break;
-    case CR_LOGF: batch_flush_op<OpLog<LOGK_E>>(q, n, tab.l, reqs, st); break;
-    case CR_LOG2F: batch_flush_op<OpLog<LOGK_2>>(q, n, tab.l, reqs, st); break;
-    case CR_LOG10F: batch_flush_op<OpLog<LOGK_10>>(q, n, tab.l, reqs, st); break;
-    case CR_LOG1PF: batch_flush_op<OpLog<LOGK_1P>>(q, n, tab.l, reqs, st); break;
-    case CR_RSQRTF: batch_flush_op<OpRsqrt>(q, n, tab.z, reqs, st); break;
-    case CR_SINF: batch_flush_op<OpTrig<TRIGK_SIN>>(q, n, tab.t, reqs, st); break;
-    case CR_COSF: batch_flush_op<OpTrig<TRIGK_COS>>(q, n, tab.t, reqs, st); break;
-    case CR_TANF: batch_flush_op<OpTrig<TRIGK_TAN>>(q, n, tab.t, reqs, st); break;
-    case CR_SINCOSF: batch_flush_sincos<SinCosF64>(q, n, tab.t, reqs, st); break;
-    case CR_ASINF: batch_flush_op<OpAtan<ATANK_ASIN>>(q, n, tab.a, reqs, st); break;
-    case CR_ACOSF: batch_flush_op<OpAtan<ATANK_ACOS>>(q, n, tab.a, reqs, st); break;
-    case CR_ATANF: batch_flush_op<OpAtan<ATANK_ATAN>>(q, n, tab.a, reqs, st); break;
-    case CR_SINHF: batch_flush_op<OpHyp<HYPK_SINH>>(q, n, tab.e, reqs, st); break;
-    case CR_COSHF: batch_flush_op<OpHyp<HYPK_COSH>>(q, n, tab.e, reqs, st); break;
-    case CR_TANHF: batch_flush_op<OpHyp<HYPK_TANH>>(q, n, tab.e, reqs, st); break;
-    case BSPLIT + CR_EXPF: batch_flush_op<OpSExp<EXPK_E>>(q, n, tab.se, reqs, st); break;
-    case BSPLIT + CR_EXP2F: batch_flush_op<OpSExp<EXPK_2>>(q, n, tab.se, reqs, st); break;
-    case BSPLIT + CR_EXP10F: batch_flush_op<OpSExp<EXPK_10>>(q, n, tab.se, reqs, st); break;
-    case BSPLIT + CR_EXPM1F: batch_flush_op<OpSExp<EXPK_EM1>>(q, n, tab.se, reqs, st); break;
-    case BSPLIT + CR_LOGF: batch_flush_op<OpSLog<LOGK_E>>(q, n, tab.sl, reqs, st); break;
-    case BSPLIT + CR_LOG2F: batch_flush_op<OpSLog<LOGK_2>>(q, n, tab.sl, reqs, st); break;
-    case BSPLIT + CR_LOG10F: batch_flush_op<OpSLog<LOGK_10>>(q, n, tab.sl, reqs, st); break;
-    case BSPLIT + CR_LOG1PF: batch_flush_op<OpSLog<LOGK_1P>>(q, n, tab.sl, reqs, st); break;
-    case BSPLIT + CR_RSQRTF: batch_flush_op<OpSRsqrt>(q, n, tab.z, reqs, st); break;
-    case BSPLIT + CR_SINF: batch_flush_op<OpSTrig<TRIGK_SIN>>(q, n, tab.st, reqs, st); break;
-    case BSPLIT + CR_COSF: batch_flush_op<OpSTrig<TRIGK_COS>>(q, n, tab.st, reqs, st); break;
-    case BSPLIT + CR_TANF: batch_flush_op<OpSTrig<TRIGK_TAN>>(q, n, tab.st, reqs, st); break;
-    case BSPLIT + CR_SINCOSF: batch_flush_sincos<SinCosSplit>(q, n, tab.st, reqs, st); break;
-    case BSPLIT + CR_ASINF: batch_flush_op<OpSAtan<ATANK_ASIN>>(q, n, tab.sa, reqs, st); break;
-    case BSPLIT + CR_ACOSF: batch_flush_op<OpSAtan<ATANK_ACOS>>(q, n, tab.sa, reqs, st); break;
-    case BSPLIT + CR_ATANF: batch_flush_op<OpSAtan<ATANK_ATAN>>(q, n, tab.sa, reqs, st); break;
-    case BSPLIT + CR_SINHF: batch_flush_op<OpSHyp<HYPK_SINH>>(q, n, tab.sh, reqs, st); break;
-    case BSPLIT + CR_COSHF: batch_flush_op<OpSHyp<HYPK_COSH>>(q, n, tab.sh, reqs, st); break;
-    case BSPLIT + CR_TANHF: batch_flush_op<OpSHyp<HYPK_TANH>>(q, n, tab.sh, reqs, st); break;
-    default: break;
-  }
+  batch_flush_op<Op>(q, n, tab, reqs, st);
   if (threadIdx.x == 0) {
     q.lanes += n;
     q.waves += (n + 63) / 64;
@@ -1047,82 +964,86 @@ __device__ __noinline__ void batch_flush(BDeferred& q, const BatchTab& tab, int 
   __syncthreads();
 }
 
+template <class SC>
+__device__ __noinline__ void batch_flush_one_sincos(BDeferred& q, const typename SC::Tab& tab,
+                                                    const BReq* reqs, DevStats* st) {
+  unsigned n = q.n < QCAP ? q.n : QCAP;
+  batch_flush_sincos<SC>(q, n, tab, reqs, st);
+  if (threadIdx.x == 0) {
+    q.lanes += n;
+    q.waves += (n + 63) / 64;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) q.n = 0;
+  __syncthreads();
+}
+
+// The batch runs one persistent kernel per function present (implementation
+// and function: the tiles are sorted by both), all captured in the plan's one
+// graph and run back to back.  Each kernel is specialised on its function, so
+// it keeps only that function's tables in LDS and only that function's
+// registers (one kernel over all functions would run every function at the
+// occupancy of the largest).  Workgroup b takes tiles t0 + b, t0 + b + grid,
+// ... of its function's contiguous range [t0, t1).
+template <class Op>
 __global__ void __launch_bounds__(BLOCK)
-    k_batch(const BReq* reqs, const BTile* tiles, long long ntiles, DevStats* st,
+    k_tiles(const BReq* reqs, const BTile* tiles, long long t0, long long t1, DevStats* st,
             unsigned flags) {
-  __shared__ BatchTab tab;
+  __shared__ typename Op::Tab tab;
   __shared__ BDeferred q;
+  Op::load(tab, threadIdx.x);
   if (threadIdx.x == 0) {
     q.n = 0;
     q.lanes = q.waves = q.esc = 0;
   }
+  __syncthreads();
   const bool force = flags & CR_FLAG_FORCE_FALLBACK;
-  // contiguous range of tiles for this workgroup
-  long long t0 = ntiles * blockIdx.x / gridDim.x, t1 = ntiles * (blockIdx.x + 1) / gridDim.x;
-  int cur = -1, iter = 0;
-  for (long long t = t0; t < t1; t++, iter++) {
+  int iter = 0;
+  for (long long t = t0 + blockIdx.x; t < t1; t += gridDim.x, iter++) {
     const BTile T = tiles[t];
-    const BReq R = reqs[T.req];
-    if (R.key != cur) {
-      __syncthreads();
-      if (cur >= 0 && q.n) batch_flush(q, tab, cur, reqs, st);
-      batch_tab_load(tab, R.key, threadIdx.x);
-      cur = R.key;
-      __syncthreads();
-    }
-    switch (cur) {
-      case CR_EXPF: batch_tile<OpExp<EXPK_E>>(R, T, tab.e, q, force, st); break;
-      case CR_EXP2F: batch_tile<OpExp<EXPK_2>>(R, T, tab.e, q, force, st); break;
-      case CR_EXP10F: batch_tile<OpExp<EXPK_10>>(R, T, tab.e, q, force, st); break;
-      case CR_EXPM1F: batch_tile<OpExp<EXPK_EM1>>(R, T, tab.e, q, force, st); break;
-      case CR_LOGF: batch_tile<OpLog<LOGK_E>>(R, T, tab.l, q, force, st); break;
-      case CR_LOG2F: batch_tile<OpLog<LOGK_2>>(R, T, tab.l, q, force, st); break;
-      case CR_LOG10F: batch_tile<OpLog<LOGK_10>>(R, T, tab.l, q, force, st); break;
-      case CR_LOG1PF: batch_tile<OpLog<LOGK_1P>>(R, T, tab.l, q, force, st); break;
-      case CR_RSQRTF: batch_tile<OpRsqrt>(R, T, tab.z, q, force, st); break;
-      case CR_SINF: batch_tile<OpTrig<TRIGK_SIN>>(R, T, tab.t, q, force, st); break;
-      case CR_COSF: batch_tile<OpTrig<TRIGK_COS>>(R, T, tab.t, q, force, st); break;
-      case CR_SINCOSF: batch_tile_sincos<SinCosF64>(R, T, tab.t, q, force, st); break;
-      case CR_TANF: batch_tile<OpTrig<TRIGK_TAN>>(R, T, tab.t, q, force, st); break;
-      case CR_ASINF: batch_tile<OpAtan<ATANK_ASIN>>(R, T, tab.a, q, force, st); break;
-      case CR_ACOSF: batch_tile<OpAtan<ATANK_ACOS>>(R, T, tab.a, q, force, st); break;
-      case CR_ATANF: batch_tile<OpAtan<ATANK_ATAN>>(R, T, tab.a, q, force, st); break;
-      case CR_SINHF: batch_tile<OpHyp<HYPK_SINH>>(R, T, tab.e, q, force, st); break;
-      case CR_COSHF: batch_tile<OpHyp<HYPK_COSH>>(R, T, tab.e, q, force, st); break;
-      case CR_TANHF: batch_tile<OpHyp<HYPK_TANH>>(R, T, tab.e, q, force, st); break;
-      case BSPLIT + CR_EXPF: batch_tile<OpSExp<EXPK_E>>(R, T, tab.se, q, force, st); break;
-      case BSPLIT + CR_EXP2F: batch_tile<OpSExp<EXPK_2>>(R, T, tab.se, q, force, st); break;
-      case BSPLIT + CR_EXP10F: batch_tile<OpSExp<EXPK_10>>(R, T, tab.se, q, force, st); break;
-      case BSPLIT + CR_EXPM1F: batch_tile<OpSExp<EXPK_EM1>>(R, T, tab.se, q, force, st); break;
-      case BSPLIT + CR_LOGF: batch_tile<OpSLog<LOGK_E>>(R, T, tab.sl, q, force, st); break;
-      case BSPLIT + CR_LOG2F: batch_tile<OpSLog<LOGK_2>>(R, T, tab.sl, q, force, st); break;
-      case BSPLIT + CR_LOG10F: batch_tile<OpSLog<LOGK_10>>(R, T, tab.sl, q, force, st); break;
-      case BSPLIT + CR_LOG1PF: batch_tile<OpSLog<LOGK_1P>>(R, T, tab.sl, q, force, st); break;
-      case BSPLIT + CR_RSQRTF: batch_tile<OpSRsqrt>(R, T, tab.z, q, force, st); break;
-      case BSPLIT + CR_SINF: batch_tile<OpSTrig<TRIGK_SIN>>(R, T, tab.st, q, force, st); break;
-      case BSPLIT + CR_COSF: batch_tile<OpSTrig<TRIGK_COS>>(R, T, tab.st, q, force, st); break;
-      case BSPLIT + CR_SINCOSF:
-        batch_tile_sincos<SinCosSplit>(R, T, tab.st, q, force, st);
-        break;
-      case BSPLIT + CR_TANF: batch_tile<OpSTrig<TRIGK_TAN>>(R, T, tab.st, q, force, st); break;
-      case BSPLIT + CR_ASINF: batch_tile<OpSAtan<ATANK_ASIN>>(R, T, tab.sa, q, force, st); break;
-      case BSPLIT + CR_ACOSF: batch_tile<OpSAtan<ATANK_ACOS>>(R, T, tab.sa, q, force, st); break;
-      case BSPLIT + CR_ATANF: batch_tile<OpSAtan<ATANK_ATAN>>(R, T, tab.sa, q, force, st); break;
-      case BSPLIT + CR_SINHF: batch_tile<OpSHyp<HYPK_SINH>>(R, T, tab.sh, q, force, st); break;
-      case BSPLIT + CR_COSHF: batch_tile<OpSHyp<HYPK_COSH>>(R, T, tab.sh, q, force, st); break;
-      case BSPLIT + CR_TANHF: batch_tile<OpSHyp<HYPK_TANH>>(R, T, tab.sh, q, force, st); break;
-      default: break;
-    }
-    // split tiles fail the rounding test more often: look at the queue every tile
-    if (cur >= BSPLIT || iter % QCHECK == QCHECK - 1) {
+    batch_tile<Op>(reqs[T.req], T, tab, q, force, st);
+    if (iter % Op::qcheck == Op::qcheck - 1) {
       __syncthreads();
       const unsigned nq = q.n;
       __syncthreads();
-      if (nq > QFLUSH) batch_flush(q, tab, cur, reqs, st);
+      if (nq > QFLUSH) batch_flush_one<Op>(q, tab, reqs, st);
     }
   }
   __syncthreads();
-  if (cur >= 0 && q.n) batch_flush(q, tab, cur, reqs, st);
+  if (q.n) batch_flush_one<Op>(q, tab, reqs, st);
+  if (threadIdx.x == 0 && q.lanes) {
+    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
+    atomicAdd(&c.fallback_lanes, (unsigned long long)q.lanes);
+    atomicAdd(&c.fallback_waves, (unsigned long long)q.waves);
+  }
+}
+
+template <class SC>
+__global__ void __launch_bounds__(BLOCK)
+    k_tiles_sincos(const BReq* reqs, const BTile* tiles, long long t0, long long t1,
+                   DevStats* st, unsigned flags) {
+  __shared__ typename SC::Tab tab;
+  __shared__ BDeferred q;
+  SC::load(tab, threadIdx.x);
+  if (threadIdx.x == 0) {
+    q.n = 0;
+    q.lanes = q.waves = q.esc = 0;
+  }
+  __syncthreads();
+  const bool force = flags & CR_FLAG_FORCE_FALLBACK;
+  int iter = 0;
+  for (long long t = t0 + blockIdx.x; t < t1; t += gridDim.x, iter++) {
+    const BTile T = tiles[t];
+    batch_tile_sincos<SC>(reqs[T.req], T, tab, q, force, st);
+    if (iter % SC::qcheck == SC::qcheck - 1) {
+      __syncthreads();
+      const unsigned nq = q.n;
+      __syncthreads();
+      if (nq > QFLUSH) batch_flush_one_sincos<SC>(q, tab, reqs, st);
+    }
+  }
+  __syncthreads();
+  if (q.n) batch_flush_one_sincos<SC>(q, tab, reqs, st);
   if (threadIdx.x == 0 && q.lanes) {
     CounterSlot& c = st->slot[blockIdx.x % NSLOT];
     atomicAdd(&c.fallback_lanes, (unsigned long long)q.lanes);
@@ -1530,6 +1451,88 @@ int build_tables(const cr_request* reqs, int32_t num, std::vector<BReq>& hr,
   return CR_OK;
 }
 
+// Contiguous tile ranges of one key (function + BSPLIT for the split
+// implementation) in the sorted tile table.
+struct BRange {
+  int key;
+  long long t0, t1;
+};
+
+std::vector<BRange> key_ranges(const std::vector<BReq>& hr, const std::vector<BTile>& ht) {
+  std::vector<BRange> rs;
+  for (long long t = 0; t < (long long)ht.size(); t++) {
+    int key = hr[ht[t].req].key;
+    if (rs.empty() || rs.back().key != key) rs.push_back({key, t, t});
+    rs.back().t1 = t + 1;
+  }
+  return rs;
+}
+
+template <class Op>
+void launch_tiles_op(const BReq* r, const BTile* t, const BRange& g, int grid, DevStats* st,
+                     unsigned flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_tiles<Op>, dim3(grid), dim3(BLOCK), 0, s, r, t, g.t0, g.t1, st, flags);
+}
+
+// Launch the kernel of one key range: grid = the function's tuned workgroups
+// per compute unit, at most one workgroup per tile.
+int launch_tiles(const BReq* r, const BTile* t, const BRange& g, DevStats* st, unsigned flags,
+                 hipStream_t s) {
+  const int func = g.key % BSPLIT, split = g.key >= BSPLIT;
+  int bpc = g_cfg_bpc[split][fidx(func)].load();
+  long long grid = (long long)num_cus() * (bpc > 0 ? bpc : default_bpc());
+  if (grid > g.t1 - g.t0) grid = g.t1 - g.t0;
+  const int G = (int)grid;
+  switch (g.key) {
+    case CR_EXPF: launch_tiles_op<OpExp<EXPK_E>>(r, t, g, G, st, flags, s); break;
+    case CR_EXP2F: launch_tiles_op<OpExp<EXPK_2>>(r, t, g, G, st, flags, s); break;
+    case CR_EXP10F: launch_tiles_op<OpExp<EXPK_10>>(r, t, g, G, st, flags, s); break;
+    case CR_EXPM1F: launch_tiles_op<OpExp<EXPK_EM1>>(r, t, g, G, st, flags, s); break;
+    case CR_LOGF: launch_tiles_op<OpLog<LOGK_E>>(r, t, g, G, st, flags, s); break;
+    case CR_LOG2F: launch_tiles_op<OpLog<LOGK_2>>(r, t, g, G, st, flags, s); break;
+    case CR_LOG10F: launch_tiles_op<OpLog<LOGK_10>>(r, t, g, G, st, flags, s); break;
+    case CR_LOG1PF: launch_tiles_op<OpLog<LOGK_1P>>(r, t, g, G, st, flags, s); break;
+    case CR_RSQRTF: launch_tiles_op<OpRsqrt>(r, t, g, G, st, flags, s); break;
+    case CR_SINF: launch_tiles_op<OpTrig<TRIGK_SIN>>(r, t, g, G, st, flags, s); break;
+    case CR_COSF: launch_tiles_op<OpTrig<TRIGK_COS>>(r, t, g, G, st, flags, s); break;
+    case CR_TANF: launch_tiles_op<OpTrig<TRIGK_TAN>>(r, t, g, G, st, flags, s); break;
+    case CR_SINCOSF:
+      hipLaunchKernelGGL(k_tiles_sincos<SinCosF64>, dim3(G), dim3(BLOCK), 0, s, r, t, g.t0, g.t1,
+                         st, flags);
+      break;
+    case CR_ASINF: launch_tiles_op<OpAtan<ATANK_ASIN>>(r, t, g, G, st, flags, s); break;
+    case CR_ACOSF: launch_tiles_op<OpAtan<ATANK_ACOS>>(r, t, g, G, st, flags, s); break;
+    case CR_ATANF: launch_tiles_op<OpAtan<ATANK_ATAN>>(r, t, g, G, st, flags, s); break;
+    case CR_SINHF: launch_tiles_op<OpHyp<HYPK_SINH>>(r, t, g, G, st, flags, s); break;
+    case CR_COSHF: launch_tiles_op<OpHyp<HYPK_COSH>>(r, t, g, G, st, flags, s); break;
+    case CR_TANHF: launch_tiles_op<OpHyp<HYPK_TANH>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_EXPF: launch_tiles_op<OpSExp<EXPK_E>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_EXP2F: launch_tiles_op<OpSExp<EXPK_2>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_EXP10F: launch_tiles_op<OpSExp<EXPK_10>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_EXPM1F: launch_tiles_op<OpSExp<EXPK_EM1>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_LOGF: launch_tiles_op<OpSLog<LOGK_E>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_LOG2F: launch_tiles_op<OpSLog<LOGK_2>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_LOG10F: launch_tiles_op<OpSLog<LOGK_10>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_LOG1PF: launch_tiles_op<OpSLog<LOGK_1P>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_RSQRTF: launch_tiles_op<OpSRsqrt>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_SINF: launch_tiles_op<OpSTrig<TRIGK_SIN>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_COSF: launch_tiles_op<OpSTrig<TRIGK_COS>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_TANF: launch_tiles_op<OpSTrig<TRIGK_TAN>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_SINCOSF:
+      hipLaunchKernelGGL(k_tiles_sincos<SinCosSplit>, dim3(G), dim3(BLOCK), 0, s, r, t, g.t0,
+                         g.t1, st, flags);
+      break;
+    case BSPLIT + CR_ASINF: launch_tiles_op<OpSAtan<ATANK_ASIN>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_ACOSF: launch_tiles_op<OpSAtan<ATANK_ACOS>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_ATANF: launch_tiles_op<OpSAtan<ATANK_ATAN>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_SINHF: launch_tiles_op<OpSHyp<HYPK_SINH>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_COSHF: launch_tiles_op<OpSHyp<HYPK_COSH>>(r, t, g, G, st, flags, s); break;
+    case BSPLIT + CR_TANHF: launch_tiles_op<OpSHyp<HYPK_TANH>>(r, t, g, G, st, flags, s); break;
+    default: return CR_E_FUNC;
+  }
+  return CR_OK;
+}
+
 }  // namespace
 
 extern "C" int cr_batch_plan_destroy(cr_batch_plan* plan);
@@ -1793,11 +1796,13 @@ int cr_batch_plan_create(const cr_request* reqs, int32_t num, unsigned flags,
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_batch, dim3(p->grid), dim3(BLOCK), 0, cs, p->d_reqs, p->d_tiles,
-                         p->ntiles, st, flags);
+      int rc2 = CR_OK;
+      for (const BRange& g2 : key_ranges(hr, ht))
+        if (rc2 == CR_OK) rc2 = launch_tiles(p->d_reqs, p->d_tiles, g2, st, flags, cs);
       hipError_t e2 = hipStreamEndCapture(cs, &g);
       e = hipGetLastError();
       if (e == hipSuccess) e = e2;
+      if (e == hipSuccess && rc2 != CR_OK) e = hipErrorInvalidValue;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
@@ -1852,6 +1857,7 @@ int cr_eval_batch(const cr_request* reqs, int32_t num, void* stream) {
   hipError_t e = hipMallocAsync((void**)&dr, hr.size() * sizeof(BReq), s);
   if (e == hipSuccess) e = hipMallocAsync((void**)&dt, ht.size() * sizeof(BTile), s);
   if (e != hipSuccess) {
+    if (dt) (void)hipFreeAsync(dt, s);
     if (dr) (void)hipFreeAsync(dr, s);
     t_last_hip = (int)e;
     return CR_E_NOMEM;
@@ -1862,9 +1868,7 @@ int cr_eval_batch(const cr_request* reqs, int32_t num, void* stream) {
   // the host vectors are freed on return: make sure the copies have read them
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) {
-    long long nt = (long long)ht.size();
-    int g = (int)(nt < grid_blocks() ? nt : grid_blocks());
-    hipLaunchKernelGGL(k_batch, dim3(g), dim3(BLOCK), 0, s, dr, dt, nt, st, 0u);
+    for (const BRange& g : key_ranges(hr, ht)) (void)launch_tiles(dr, dt, g, st, 0u, s);
     e = hipGetLastError();
   }
   (void)hipFreeAsync(dt, s);
