@@ -15,8 +15,11 @@ the CPU oracle (oracle/) on a bounded sample of the same inputs.
 
 other_workloads (left out with --headline-only) reports, outside the headline
 value: the trig/inverse-trig/hyperbolic family at the same size, binary64
-exp/log on 2^24 inputs each, and the ragged batch of 4096 mixed requests
-evaluated by one graph launch per step (plan creation timed separately).
+exp/log on 2^24 inputs each, the paper's GPU metric (correctly rounded over
+the platform's ~1-ulp library functions for expf, logf, sincosf, exp, log),
+the ragged batch of 4096 mixed requests evaluated by one graph launch per step
+(plan creation timed separately), and the binary32-only implementation on the
+same workloads.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n LOG2N]
 """
@@ -93,6 +96,50 @@ def bench_family(torch, crmath, inputs, funcs, n, impl, steps, warmup, stream, s
             "per_func": res}
 
 
+PAPER_GPU_FUNCS = ["expf", "logf", "sincosf", "exp", "log"]
+
+
+def bench_vs_ulp(torch, crmath, inputs, n, steps, warmup, stream):
+    """The paper's GPU metric (Sec. III-C, Tables III, IV): correctly rounded
+    throughput over the platform's ~1-ulp library functions (HIP's device math
+    library, in a map kernel of the same launch shape), on the same inputs."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2605_15547_amd", "libcr_ulpref.so")
+    if not os.path.exists(path):
+        return None
+    R = ctypes.CDLL(path)
+    R.cr_ref_eval.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                              ctypes.c_void_p]
+    sp = crmath._stream_ptr(stream)
+    out = {}
+    for f in PAPER_GPU_FUNCS:
+        m = n >> 2 if f in ("exp", "log") else n
+        x = inputs.workload_f64(f, m) if f in ("exp", "log") else inputs.workload_f32(f, m)
+        xt = torch.from_numpy(x).cuda()
+        ot = torch.empty(2 * m if f == "sincosf" else m, dtype=xt.dtype, device="cuda")
+        fid = crmath.FUNC_ID[f]
+        runs = {"cr": lambda: crmath.eval_ptr(f, xt.data_ptr(), ot.data_ptr(), m, 1, 0, sp),
+                "ulp": lambda: R.cr_ref_eval(fid, xt.data_ptr(), ot.data_ptr(), m, sp)}
+        settle(lambda: (runs["cr"](), runs["ulp"]()), 0.3, torch)
+        rate = {}
+        for k, fn in runs.items():
+            for _ in range(warmup):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rate[k] = m / (e0.elapsed_time(e1) / steps * 1e-3) / 1e9
+        out[f] = {"cr_gelem_s": round(rate["cr"], 2), "ulp_gelem_s": round(rate["ulp"], 2),
+                  "ratio": round(rate["cr"] / rate["ulp"], 3)}
+        del xt, ot
+    torch.cuda.empty_cache()
+    log("bench: vs 1-ulp library", out)
+    return out
+
+
 def bench_batch(torch, crmath, inputs, steps, warmup, stream, impl=1):
     """The ragged batch: 4096 requests of mixed binary32 functions, lengths
     log-uniform in [1, 2^20], evaluated by one graph launch per step."""
@@ -142,7 +189,7 @@ def kernel_source_hash():
     import glob
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2605_15547_amd", "csrc", "*"))):
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2605_15547_amd", "csrc", "cr_*"))):
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -283,6 +330,8 @@ def main():
             torch, crmath, inputs, TRIG, n, a.impl, a.steps, a.warmup, stream)
         extra["binary64_exp_log"] = bench_family(
             torch, crmath, inputs, ["exp", "log"], 1 << 24, 0, a.steps, a.warmup, stream)
+        extra["vs_ulp_library"] = bench_vs_ulp(torch, crmath, inputs, n, a.steps, a.warmup,
+                                               stream)
         extra["ragged_batch"] = bench_batch(torch, crmath, inputs, a.steps, a.warmup, stream)
         extra["ragged_batch_split_f32"] = bench_batch(torch, crmath, inputs, a.steps, a.warmup,
                                                       stream, impl=2)

@@ -18,6 +18,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcr.so")
+REF_LIB = os.path.join(PKG, "libcr_ulpref.so")
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -45,5 +46,18 @@ def build(verbose=False, extra=()):
     return LIB
 
 
+def build_ref(verbose=False):
+    """The platform's ~1-ulp functions as maps (benchmark comparison only)."""
+    src = os.path.join(CSRC, "ulp_ref.hip")
+    tmp = REF_LIB + ".tmp%d" % os.getpid()
+    cmd = [hipcc()] + HIPCC_FLAGS + [src, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd, cwd=CSRC)
+    os.replace(tmp, REF_LIB)
+    return REF_LIB
+
+
 if __name__ == "__main__":
     build(verbose=True, extra=sys.argv[1:])
+    build_ref(verbose=True)
