@@ -38,11 +38,12 @@ __device__ __forceinline__ void log_tab_load(LogTab& t, int tid) {
   }
 }
 
-// Fast-path error: Q approximation < 2^-60 |t|; the inner sum (|K t + ...| <
-// 0.1) carries one rounding each for t Q and the additions (< 2^-56 absolute);
-// the last addition 1/2 ulp.  |y| >= 0.0128 except on the two sub-intervals
-// around 1 where y = K t + t Q(t) has relative error < 2^-52.  That is below
-// 2 ulps; the test uses 8 (2^3) to absorb the binade of the computed value.
+// Fast-path error: Q approximation < 2^-57.6 |t| (|t| <= 1/16); the inner sum
+// (|K t + ...| < 0.1) carries one rounding each for t Q and the additions
+// (< 2^-56 absolute); the last addition 1/2 ulp.  |y| >= 0.0128 except on the
+// two sub-intervals around 1, where y = K t + t Q(t) (K >= 0.434) has relative
+// error < 2^-51.7.  That is below 2.5 ulps; the test uses 8 (2^3) to absorb the
+// binade of the computed value.
 constexpr int LOG_LOG2E = 3;
 
 template <int K>

@@ -251,11 +251,13 @@ def gen_log():
     a, b = tmin * mp.mpf("1.0001"), tmax * mp.mpf("1.0001")
     for name, inv_ln, K in bases:
         g = (lambda il, KK: (lambda t: (mp.log1p(t) * il / t - KK) if t != 0 else il - KK))(inv_ln, K)
-        for deg in range(9, 16):
+        # the fast path's test allows 8 ulps; Q within 2^-57 keeps the whole
+        # fast-path error below about 2.5 ulps (see cr_f32_log.h)
+        for deg in range(6, 16):
             cs = lawson_fit(g, lambda t: mp.mpf(1), a, b, list(range(deg + 1)), npts=160, iters=16)
             cd = [d(v) for v in cs]
             err = max_err(lambda t: g(t) - sum(mp.mpf(cd[k]) * t ** k for k in range(len(cd))), a, b)
-            if err < mp.mpf(2) ** -62:
+            if err < mp.mpf(2) ** -57:
                 break
         bound = err * mp.mpf("1.25")
         emit("// log_b(1+t) = K t + t Q(t), K = %s, t in [%s, %s]; |Q error| <= 2^%.2f"
