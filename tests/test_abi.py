@@ -139,3 +139,26 @@ def test_tuning_table(L, tmp_path):
     assert at(0, 5, vp(0x1000), vp(0x2000), 8, 1, None, None) == -5
     assert at(0, 0, vp(0x1001), vp(0x2000), 8, 1, None, None) == -4
     assert at(0, 0, vp(0x1000), vp(0x1004), 8, 1, None, None) == -3
+
+
+def test_committed_tuning_file_is_valid(L):
+    """The launch configurations shipped for MI355X load cleanly and cover
+    every function of both implementations."""
+    from paper_2605_15547_amd import crmath as C
+    path = os.path.join(ROOT, "paper_2605_15547_amd", "tuning", "mi355x.txt")
+    assert os.path.exists(path)
+    C.tune_reset()
+    try:
+        C.tune_load(path)
+        seen = set()
+        for line in open(path):
+            if line.strip() and not line.lstrip().startswith("#"):
+                f, impl, v, b = line.split()
+                seen.add((f, impl))
+                im = C.IMPL_SPLIT_F32 if impl == "split" else C.IMPL_F64_INTERNAL
+                assert C.tune_get(f, im) == (int(v), int(b))
+        for f in C.FUNCS32:
+            assert (f, "f64") in seen and (f, "split") in seen, f
+        assert ("exp", "f64") in seen and ("log", "f64") in seen
+    finally:
+        C.tune_reset()
