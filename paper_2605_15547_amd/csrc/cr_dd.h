@@ -52,6 +52,21 @@ __device__ __forceinline__ dd dd_add(dd x, dd y) {
   return fast_two_sum(v.hi, w);
 }
 
+// double-word + double-word when |x.hi| >= |y.hi| (or x.hi == 0) and the sum
+// does not cancel: Fast2Sum of the high parts, the low parts added once
+// (relative error a few u^2; 8 operations instead of 20)
+__device__ __forceinline__ dd dd_add_ord(dd x, dd y) {
+  dd s = fast_two_sum(x.hi, y.hi);
+  return fast_two_sum(s.hi, s.lo + (x.lo + y.lo));
+}
+
+// double-word + double-word without an ordering condition, for sums that do
+// not cancel: TwoSum of the high parts, the low parts added once
+__device__ __forceinline__ dd dd_add_nc(dd x, dd y) {
+  dd s = two_sum(x.hi, y.hi);
+  return fast_two_sum(s.hi, s.lo + (x.lo + y.lo));
+}
+
 // double-word * double (relative error <= 2u^2)
 __device__ __forceinline__ dd dd_mul_d(dd x, double y) {
   dd c = two_prod(x.hi, y);

@@ -71,7 +71,7 @@ __device__ __forceinline__ double exp64_fast(double x, const Exp64Tab& tb, bool&
   int m = k >> 8;
   double4 A = tb.t1[(k >> 4) & 15], B = tb.t2[k & 15];
   dd T = dd_mul(dd{A.x, A.y}, dd{B.x, B.y});
-  dd y = dd_add(T, dd_mul(T, q));  // T e^r, in [2^-1/512, 2)
+  dd y = dd_add_ord(T, dd_mul(T, q));  // T e^r, in [2^-1/512, 2); |T q| < 2^-9 |T|
   double res;
   double e = fabs(y.hi) * EXP64_EPS;
   if (m >= -1021) {  // normal result: round in the unscaled domain, then scale
@@ -186,12 +186,14 @@ __device__ __forceinline__ double log64_fast(double x, const Log64Tab& tb, bool&
 #pragma unroll
   for (int i = LOG64_S_DEG - 1; i >= 0; i--) sp = fma(sp, t.hi, LOG64_S[i]);
   double tail = t2.hi * t2.hi * sp;
-  dd l1 = dd_add(t, dd{-0.5 * t2.hi, -0.5 * t2.lo});
-  l1 = dd_add(l1, dd_add_d(b3, tail));
-  // e' ln2 - ln c_j
+  // |t| <= 1/16: t dominates t^2/2, which dominates t^3/3 + t^4 S(t)
+  dd l1 = dd_add_ord(t, dd{-0.5 * t2.hi, -0.5 * t2.lo});
+  l1 = dd_add_ord(l1, dd{b3.hi, b3.lo + tail});
+  // e' ln2 - ln c_j: |e' ln2| >= ln2 > |ln c_j| unless e' = 0; the total does
+  // not cancel (|y| >= 0.03 unless e' = 0 and c_j = 1, where y = l1 exactly)
   double ed = (double)S.e2;
   dd el = dd_mul_d(dd{LN2_TD[0].x, LN2_TD[0].y}, ed);
-  dd y = dd_add(dd_add(el, dd{L.x, L.y}), l1);
+  dd y = dd_add_nc(dd_add_ord(el, dd{L.x, L.y}), l1);
   double e = fabs(y.hi) * LOG64_EPS;
   double a = y.hi + (y.lo - e);
   double b = y.hi + (y.lo + e);
