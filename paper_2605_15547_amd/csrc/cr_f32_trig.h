@@ -89,19 +89,21 @@ struct SinCosTheta {
 };
 
 __device__ __forceinline__ SinCosTheta theta_of(int q, const TrigTab& tb) {
-  double4 T = tb.sc[q & 15];
-  int quad = q >> 4;
+  // quad 0: (S, C); 1: (C, -S); 2: (-S, -C); 3: (-C, S).  The swap of odd
+  // quadrants picks which half of the 32-byte table row is read for each
+  // pair (an address offset instead of selects on four doubles), and the
+  // signs are flipped on the sign bits.
+  const int quad = q >> 4;
+  const int swap = quad & 1;
+  const double2* row = reinterpret_cast<const double2*>(&tb.sc[q & 15]);
+  const double2 S = row[swap], C = row[swap ^ 1];
+  const long long ms = (long long)(quad >= 2) << 63;
+  const long long mc = (long long)(quad == 1 || quad == 2) << 63;
   SinCosTheta r;
-  // quad 0: (S, C); 1: (C, -S); 2: (-S, -C); 3: (-C, S)
-  bool swap = quad & 1;
-  double sh = swap ? T.z : T.x, sl = swap ? T.w : T.y;
-  double ch = swap ? T.x : T.z, cl = swap ? T.y : T.w;
-  bool negs = quad >= 2;
-  bool negc = quad == 1 || quad == 2;
-  r.sh = negs ? -sh : sh;
-  r.sl = negs ? -sl : sl;
-  r.ch = negc ? -ch : ch;
-  r.cl = negc ? -cl : cl;
+  r.sh = __longlong_as_double(__double_as_longlong(S.x) ^ ms);
+  r.sl = __longlong_as_double(__double_as_longlong(S.y) ^ ms);
+  r.ch = __longlong_as_double(__double_as_longlong(C.x) ^ mc);
+  r.cl = __longlong_as_double(__double_as_longlong(C.y) ^ mc);
   return r;
 }
 
@@ -125,9 +127,10 @@ __device__ __forceinline__ TrigFast trig_fast_core(float xf, const TrigTab& tb) 
   double axd = (double)bits_f32(ax);
   bool small = axd < PI64;
   Reduced R = payne_hanek(ax, tb.w);
-  // f = fhi 2^-64 (+ flo 2^-128, ignored here: < 2^-64)
-  double fh = (double)(R.fhi >> 11) * 0x1p-53;
-  double fl = (double)(R.fhi & 0x7ff) * 0x1p-64;
+  // f = fhi 2^-64 (+ flo 2^-128, ignored here: < 2^-64), as the exact sum of
+  // its signed high and unsigned low 32-bit halves
+  double fh = (double)(int)(R.fhi >> 32) * 0x1p-32;
+  double fl = (double)(uint32_t)R.fhi * 0x1p-64;
   double r = fma(fh, PI32_HI, fma(fh, PI32_MID, fl * PI32_HI));
   int q = R.q;
   if (small) {
