@@ -102,13 +102,15 @@ __device__ __forceinline__ STrigCore strig_core(float xf, const STrigTab& tb) {
   cm.lo += -0.5f * z.lo + (c4.lo + c6);
 
   // theta = q pi/32 = quad pi/2 + j pi/32
-  float4 T = tb.sc[q & 15];
-  int quad = q >> 4;
-  bool swap = quad & 1;
-  ff Sv = swap ? ff{T.z, T.w} : ff{T.x, T.y};
-  ff Cv = swap ? ff{T.x, T.y} : ff{T.z, T.w};
-  if (quad >= 2) Sv = {-Sv.hi, -Sv.lo};
-  if (quad == 1 || quad == 2) Cv = {-Cv.hi, -Cv.lo};
+  // the odd quadrants' swap picks which half of the table row is read
+  const int quad = q >> 4;
+  const int swap = quad & 1;
+  const float2* row = reinterpret_cast<const float2*>(&tb.sc[q & 15]);
+  const float2 S2 = row[swap], C2 = row[swap ^ 1];
+  const uint32_t ms = (uint32_t)(quad >= 2) << 31;
+  const uint32_t mc = (uint32_t)(quad == 1 || quad == 2) << 31;
+  ff Sv = {bits_f32(f32_bits(S2.x) ^ ms), bits_f32(f32_bits(S2.y) ^ ms)};
+  ff Cv = {bits_f32(f32_bits(C2.x) ^ mc), bits_f32(f32_bits(C2.y) ^ mc)};
 
   STrigCore o;
   o.small = small;
