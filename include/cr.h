@@ -129,8 +129,9 @@ int cr_batch_plan_create(const cr_request *reqs, int32_t num, unsigned flags,
                          cr_batch_plan **plan);
 /* Launch the plan's graph on the stream (asynchronous, stream-ordered).  The
  * graph holds one persistent kernel per (implementation, function) present,
- * run back to back, each over its own contiguous range of 2048-element tiles
- * (requests are sorted by implementation and function when the plan is made). */
+ * each over its own contiguous range of 2048-element tiles (requests are
+ * sorted by implementation and function when the plan is made), spread over
+ * four parallel branches that join before the launch completes. */
 int cr_batch_plan_launch(cr_batch_plan *plan, void *stream);
 /* Release the plan (synchronises with its last launch first). */
 int cr_batch_plan_destroy(cr_batch_plan *plan);

@@ -120,18 +120,18 @@ __device__ __forceinline__ LogSetup log_setup(float xf, const LogTab& tb) {
   int fold = j >> 3;
   S.e2 = ((hi >> 20) & 0x7ff) - 1023 + fold;
   S.m = __hiloint2double((hi & 0x000fffff) | ((1023 - fold) << 20), __double2loint(S.u));
+  S.near = 0;
+  if (K == LOGK_1P) {
+    // near 0, log1p(x) is evaluated on t = x itself (1 + x may be inexact):
+    // table row 0 (c = 1, log c = 0) and e' = 0
+    S.near = (x >= -0.03125) & (x < 0.0625);
+    j = S.near ? 0 : j;
+    S.e2 = S.near ? 0 : S.e2;
+  }
   S.c = tb.c[j];
   S.L = tb.L[j];
   S.t = fma(S.m, S.c, -1.0);
-  S.near = 0;
-  if (K == LOGK_1P) {
-    S.near = (x >= -0.03125) & (x < 0.0625);
-    if (S.near) {
-      S.t = x;
-      S.e2 = 0;
-      S.L = make_double2(0.0, 0.0);
-    }
-  }
+  if (K == LOGK_1P && S.near) S.t = x;
   return S;
 }
 

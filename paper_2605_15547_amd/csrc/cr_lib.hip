@@ -1474,13 +1474,16 @@ void launch_tiles_op(const BReq* r, const BTile* t, const BRange& g, int grid, D
   hipLaunchKernelGGL(k_tiles<Op>, dim3(grid), dim3(BLOCK), 0, s, r, t, g.t0, g.t1, st, flags);
 }
 
-// Launch the kernel of one key range: grid = the function's tuned workgroups
-// per compute unit, at most one workgroup per tile.
+// Workgroups per compute unit of each batch kernel.  The plan's graph runs up
+// to four of them at a time (parallel branches), so together they hold about
+// 16 workgroups per CU; measured on the 4096-request workload: 1 -> 361,
+// 2 -> 413, 4 -> 428, 8 -> 422, 16 -> 411, 32 -> 385 Gelem/s.
+constexpr int BATCH_BPC = 4;
+
+// Launch the kernel of one key range (at most one workgroup per tile).
 int launch_tiles(const BReq* r, const BTile* t, const BRange& g, DevStats* st, unsigned flags,
                  hipStream_t s) {
-  const int func = g.key % BSPLIT, split = g.key >= BSPLIT;
-  int bpc = g_cfg_bpc[split][fidx(func)].load();
-  long long grid = (long long)num_cus() * (bpc > 0 ? bpc : default_bpc());
+  long long grid = (long long)num_cus() * BATCH_BPC;
   if (grid > g.t1 - g.t0) grid = g.t1 - g.t0;
   const int G = (int)grid;
   switch (g.key) {
@@ -1789,23 +1792,48 @@ int cr_batch_plan_create(const cr_request* reqs, int32_t num, unsigned flags,
   if (e == hipSuccess && !ht.empty())
     e = hipMemcpy(p->d_tiles, ht.data(), ht.size() * sizeof(BTile), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
-  // capture the single launch in a graph (a private stream at default priority)
+  // Capture the launches in a graph (private streams at default priority).
+  // The per-function kernels are spread over NBRANCH parallel branches (a
+  // fork from the origin stream and a join back to it) so that one kernel's
+  // tail overlaps the next kernel's start.
   if (e == hipSuccess && p->grid > 0) {
-    hipStream_t cs = nullptr;
+    constexpr int NBRANCH = 4;
+    hipStream_t cs = nullptr, side[NBRANCH] = {};
+    hipEvent_t fork = nullptr, join[NBRANCH] = {};
     hipGraph_t g = nullptr;
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    for (int b = 0; b < NBRANCH && e == hipSuccess; b++) {
+      e = hipStreamCreateWithFlags(&side[b], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&join[b], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      int rc2 = CR_OK;
-      for (const BRange& g2 : key_ranges(hr, ht))
-        if (rc2 == CR_OK) rc2 = launch_tiles(p->d_reqs, p->d_tiles, g2, st, flags, cs);
+      hipError_t ec = hipEventRecord(fork, cs);
+      for (int b = 0; b < NBRANCH && ec == hipSuccess; b++)
+        ec = hipStreamWaitEvent(side[b], fork, 0);
+      int rc2 = CR_OK, i = 0;
+      if (ec == hipSuccess)
+        for (const BRange& g2 : key_ranges(hr, ht))
+          if (rc2 == CR_OK)
+            rc2 = launch_tiles(p->d_reqs, p->d_tiles, g2, st, flags, side[i++ % NBRANCH]);
+      for (int b = 0; b < NBRANCH && ec == hipSuccess; b++) {
+        ec = hipEventRecord(join[b], side[b]);
+        if (ec == hipSuccess) ec = hipStreamWaitEvent(cs, join[b], 0);
+      }
       hipError_t e2 = hipStreamEndCapture(cs, &g);
       e = hipGetLastError();
+      if (e == hipSuccess) e = ec;
       if (e == hipSuccess) e = e2;
       if (e == hipSuccess && rc2 != CR_OK) e = hipErrorInvalidValue;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
+    if (fork) (void)hipEventDestroy(fork);
+    for (int b = 0; b < NBRANCH; b++) {
+      if (join[b]) (void)hipEventDestroy(join[b]);
+      if (side[b]) (void)hipStreamDestroy(side[b]);
+    }
     if (cs) (void)hipStreamDestroy(cs);
   }
   if (e != hipSuccess) {
