@@ -9,10 +9,11 @@
 //     log_b(x) = e' log_b(2) + (-log_b c_j) + K t + t Q(t),
 // with K = 1/ln b on 20 bits (K t exact) and Q a minimax polynomial on
 // t in [-1/32, 1/16].  c_j = 1 on the two sub-intervals next to 1, so for x
-// near 1 the result is K t + t Q(t) with no cancellation.  log1pf uses t = x
-// directly when x is in [-1/32, 1/16) and the same reduction of u = 1 + x
-// otherwise (u is exact for |x| <= 2^29; beyond, the rounding of u moves
-// log(u) by less than 2^-53 and |log(u)| > 20).
+// near 1 the result is K t + t Q(t) with no cancellation.  log1pf reduces
+// u = RN(1 + x) the same way and moves the rounding error of u (exact by
+// Fast2Sum for |x| <= 1) into t: t = m c_j - 1 + (1 + x - u) c_j 2^-e'.  Near
+// x = 0 this gives c_j = 1, e' = 0 and t = x exactly; for |x| > 1 the term is
+// below 2^-53 of u and only approximate, which moves log(u) by < 2^-52.
 //
 // The binary64 fast path ends with the rounding test of cr_round.h; lanes that
 // fail it run the accurate double-double path below (log1p(t) = 2 atanh(t/(2+t))
@@ -106,7 +107,7 @@ __device__ __forceinline__ dd log1p_dd(dd t) {
 struct LogSetup {
   double u, m, c, t;
   double2 L;
-  int e2, near;
+  int e2;
 };
 
 template <int K>
@@ -120,34 +121,32 @@ __device__ __forceinline__ LogSetup log_setup(float xf, const LogTab& tb) {
   int fold = j >> 3;
   S.e2 = ((hi >> 20) & 0x7ff) - 1023 + fold;
   S.m = __hiloint2double((hi & 0x000fffff) | ((1023 - fold) << 20), __double2loint(S.u));
-  S.near = 0;
-  if (K == LOGK_1P) {
-    // near 0, log1p(x) is evaluated on t = x itself (1 + x may be inexact):
-    // table row 0 (c = 1, log c = 0) and e' = 0
-    S.near = (x >= -0.03125) & (x < 0.0625);
-    j = S.near ? 0 : j;
-    S.e2 = S.near ? 0 : S.e2;
-  }
   S.c = tb.c[j];
   S.L = tb.L[j];
   S.t = fma(S.m, S.c, -1.0);
-  if (K == LOGK_1P && S.near) S.t = x;
+  if (K == LOGK_1P) {
+    // the rounding error of u = 1 + x, scaled like m (Fast2Sum, |x| <= 1)
+    const double ulo = (x - (S.u - 1.0)) * pow2i(-S.e2);
+    S.t = fma(ulo, S.c, S.t);
+  }
   return S;
 }
 
-// NaN (quieted), u <= 0 (-inf at 0, NaN below), u = +inf, log1p(+-0) = +-0.
+// NaN (quieted), u <= 0 (-inf at 0, NaN below), u = +inf, log1p(+-0) = +-0,
+// decided on the binary32 argument (u = 1 + x is exact for x in [-1, 1], so
+// u <= 0 exactly when x <= -1).
 // Branch-free: res is always written (meaningful only when true is returned).
 template <int K>
-__device__ __forceinline__ bool log_special(float xf, double u, float& res) {
+__device__ __forceinline__ bool log_special(float xf, float& res) {
   const bool nan = xf != xf;
+  const float lim = K == LOGK_1P ? -1.0f : 0.0f;  // log1p(-1) = log(+-0) = -inf
   const bool zero1p = K == LOGK_1P && xf == 0.0f;
-  const bool nonpos = !(u > 0.0);
-  const bool inf = u == INFINITY;
-  float v = inf ? INFINITY : bits_f32(0x7fc00000u);
-  v = u == 0.0 ? -INFINITY : v;
+  const bool dom = xf <= lim;
+  const bool inf = xf == INFINITY;
+  float v = inf ? INFINITY : (xf == lim ? -INFINITY : bits_f32(0x7fc00000u));
   v = zero1p ? xf : v;
   res = nan ? bits_f32(f32_bits(xf) | 0x00400000u) : v;
-  return nan | zero1p | nonpos | inf;
+  return nan | zero1p | dom | inf;
 }
 
 template <int K>
@@ -161,7 +160,7 @@ __device__ __forceinline__ float log_fast(float xf, const LogTab& tb, bool& ok) 
   double yh = A.hi + fma(log_K<K>(), t, inner);
   float res = round_f32_fast<LOG_LOG2E>(yh, ok);
   float sp;
-  if (log_special<K>(xf, S.u, sp)) {
+  if (log_special<K>(xf, sp)) {
     res = sp;
     ok = true;
   }
@@ -175,19 +174,13 @@ template <int K>
 __device__ __noinline__ AccResult log_accurate(float xf, const LogTab& tb) {
   LogSetup S = log_setup<K>(xf, tb);
   float sp;
-  if (log_special<K>(xf, S.u, sp)) return {sp, 1};
-  dd t;
-  if (S.near) {
-    t = {S.t, 0.0};
-  } else {
-    dd p = two_prod(S.m, S.c);
-    t = fast_two_sum(p.hi - 1.0, p.lo);  // p.hi - 1 is exact (p.hi in [0.96, 1.07])
-    if (K == LOGK_1P) {
-      // (1 + x) - u exactly (Fast2Sum: |x| >= 1 whenever u is inexact), scaled like m
-      double x = (double)xf;
-      double ulo = (1.0 - (S.u - x)) * pow2i(-S.e2);
-      t = dd_add_d(t, ulo * S.c);
-    }
+  if (log_special<K>(xf, sp)) return {sp, 1};
+  dd p = two_prod(S.m, S.c);
+  dd t = fast_two_sum(p.hi - 1.0, p.lo);  // p.hi - 1 is exact (p.hi in [0.96, 1.07])
+  if (K == LOGK_1P) {
+    // (1 + x) - u exactly (TwoSum), scaled like m
+    const double ulo = two_sum(1.0, (double)xf).lo * pow2i(-S.e2);
+    t = dd_add_d(t, ulo * S.c);
   }
   dd l = log1p_dd(t);
   if (K == LOGK_2) l = dd_mul(l, dd{INV_LN2_HI, INV_LN2_LO});
