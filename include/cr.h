@@ -199,9 +199,9 @@ int cr_tune_save(const char *path);
 /* Time every variant x grid size {2, 4, 8, 16, 32 workgroups per CU} of
  * (func_id, impl) on the caller's device buffers in/out (n elements, the same
  * conventions as cr_eval_ex; out is overwritten): about 100 ms of launches
- * first so the clocks settle, then two passes over the space (reps timed
+ * first so the clocks settle, then three passes over the space (reps timed
  * launches per configuration after one untimed one, reps <= 0: 10), keeping
- * each configuration's faster pass, and install the fastest.  Synchronizes the
+ * each configuration's median pass, and install the fastest.  Synchronizes the
  * stream; adds its launches to the statistics counters.  best_gelem_s (may be
  * NULL) receives the winner's rate in 10^9 elements per second. */
 int cr_autotune(int func_id, int impl, const void *in, void *out, size_t n, int reps,

@@ -19,7 +19,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--log2n", type=int, default=26)
-    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=10)
     a = ap.parse_args()
     import torch
     from paper_2605_15547_amd import crmath, inputs

@@ -1721,15 +1721,22 @@ int cr_autotune(int func_id, int impl, const void* in, void* out, size_t n, int 
     rc = time_cfg(0, 0, ms);
     busy += ms > 0.0f ? ms : 100.0f;
   }
-  // two passes over the space, in opposite orders; the minimum counts
-  std::vector<float> best_of(nv * NB, 0.0f);
-  for (int pass = 0; pass < 2 && rc == CR_OK; pass++) {
+  // three passes over the space, alternating in order; the median counts
+  constexpr int NPASS = 3;
+  std::vector<float> times((size_t)nv * NB * NPASS, 0.0f);
+  for (int pass = 0; pass < NPASS && rc == CR_OK; pass++) {
     for (int c = 0; c < nv * NB && rc == CR_OK; c++) {
-      const int idx = pass ? nv * NB - 1 - c : c;
+      const int idx = (pass & 1) ? nv * NB - 1 - c : c;
       float ms = 0.0f;
       rc = time_cfg(idx / NB, BPCS[idx % NB], ms);
-      if (rc == CR_OK && (best_of[idx] == 0.0f || ms < best_of[idx])) best_of[idx] = ms;
+      times[(size_t)idx * NPASS + pass] = ms;
     }
+  }
+  std::vector<float> best_of(nv * NB, 0.0f);
+  for (int idx = 0; idx < nv * NB && rc == CR_OK; idx++) {
+    float* t = &times[(size_t)idx * NPASS];
+    std::sort(t, t + NPASS);
+    best_of[idx] = t[NPASS / 2];
   }
   float best_ms = 0.0f;
   int best_v = 0, best_b = 0;
