@@ -292,7 +292,7 @@ struct OpHyp {
 // Block-level bookkeeping of the accurate path, kept in LDS.
 struct Deferred {
   unsigned n;                 // entries in the queue
-  unsigned lanes, waves, esc; // counters of this workgroup
+  unsigned lanes, waves;      // counters of this workgroup
   unsigned idx[QCAP];         // element index (relative to the launch)
   float x[QCAP];              // the input value (the output may alias it)
 };
@@ -302,29 +302,46 @@ __device__ __forceinline__ void note_escape(DevStats* st, long long idx) {
   if (slot < 16) st->escape_index[slot] = (unsigned long long)idx;
 }
 
-// Run the accurate path on every queued element, 256 at a time (whole waves),
-// then empty the queue.  Called by all threads of the block.
-template <class Op>
-__device__ __noinline__ void flush_queue(Deferred& q, const typename Op::Tab& tab, float* out,
-                                         DevStats* st, long long elem_base) {
+// Runs body(k) on every queued entry k, 256 at a time (whole waves).
+// FINAL = false: then empties the queue; all threads of the workgroup take
+// part.  FINAL = true: the workgroup's last flush, after its final barrier; no
+// barrier follows, so waves with no entry retire at once and free their slots
+// for the next workgroup while the others run the accurate path, and the
+// workgroup's counters go to the device statistics.
+template <bool FINAL, class Q, class Body>
+__device__ __forceinline__ void run_queue(Q& q, DevStats* st, Body body) {
   // q.n counts every enqueue attempt; entries past QCAP were never stored
   // (those elements took the accurate path in place), so only QCAP are valid
-  unsigned n = q.n < QCAP ? q.n : QCAP;
-  for (unsigned k = threadIdx.x; k < n; k += BLOCK) {
+  const unsigned n = q.n < QCAP ? q.n : QCAP;
+  for (unsigned k = threadIdx.x; k < n; k += BLOCK) body(k);
+  if (FINAL) {
+    if (threadIdx.x == 0) {
+      const unsigned lanes = q.lanes + n, waves = q.waves + (n + 63) / 64;
+      if (lanes) {
+        CounterSlot& c = st->slot[blockIdx.x % NSLOT];
+        atomicAdd(&c.fallback_lanes, (unsigned long long)lanes);
+        atomicAdd(&c.fallback_waves, (unsigned long long)waves);
+      }
+    }
+  } else {
+    if (threadIdx.x == 0) {
+      q.lanes += n;
+      q.waves += (n + 63) / 64;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) q.n = 0;
+    __syncthreads();
+  }
+}
+
+template <class Op, bool FINAL = false>
+__device__ __forceinline__ void flush_queue(Deferred& q, const typename Op::Tab& tab, float* out,
+                                            DevStats* st, long long elem_base) {
+  run_queue<FINAL>(q, st, [&](unsigned k) {
     AccResult a = Op::accurate(q.x[k], tab);
     out[q.idx[k]] = a.r;
-    if (!a.ok) {
-      atomicAdd(&q.esc, 1u);
-      note_escape(st, elem_base + q.idx[k]);
-    }
-  }
-  if (threadIdx.x == 0) {
-    q.lanes += n;
-    q.waves += (n + 63) / 64;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) q.n = 0;
-  __syncthreads();
+    if (!a.ok) note_escape(st, elem_base + q.idx[k]);
+  });
 }
 
 // ---------------------------------------------------------------- kernels
@@ -359,7 +376,7 @@ __global__ void __launch_bounds__(BLOCK)
   if (!TP) Op::load(lds_tab, threadIdx.x);
   if (threadIdx.x == 0) {
     q.n = 0;
-    q.lanes = q.waves = q.esc = 0;
+    q.lanes = q.waves = 0;
   }
   __syncthreads();
   const bool force = flags & CR_FLAG_FORCE_FALLBACK;
@@ -433,10 +450,7 @@ __global__ void __launch_bounds__(BLOCK)
               AccResult a = Op::accurate(x, tab);
               e[c] = a.r;
               atomicAdd(&q.lanes, 1u);
-              if (!a.ok) {
-                atomicAdd(&q.esc, 1u);
-                note_escape(st, elem_base + 4 * i + c);
-              }
+              if (!a.ok) note_escape(st, elem_base + 4 * i + c);
             }
           }
         }
@@ -457,13 +471,7 @@ __global__ void __launch_bounds__(BLOCK)
     }
   }
   __syncthreads();
-  // after the barrier above nothing else changes q.n: uniform
-  if (q.n) flush_queue<Op>(q, tab, outf, st, elem_base);
-  if (threadIdx.x == 0 && q.lanes) {
-    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
-    atomicAdd(&c.fallback_lanes, (unsigned long long)q.lanes);
-    atomicAdd(&c.fallback_waves, (unsigned long long)q.waves);
-  }
+  flush_queue<Op, true>(q, tab, outf, st, elem_base);
 }
 
 // Scalar form for unaligned heads, ragged tails and pointers whose alignment
@@ -499,26 +507,16 @@ __global__ void __launch_bounds__(BLOCK)
 
 // sincosf: the map kernel with two planar outputs (sin block, cos block), both
 // 16-byte aligned (the host checks; otherwise the scalar form below runs).
-template <class SC>
-__device__ __noinline__ void flush_queue_sincos(Deferred& q, const typename SC::Tab& tab, float* os,
-                                                float* oc, DevStats* st, long long elem_base) {
-  unsigned n = q.n < QCAP ? q.n : QCAP;
-  for (unsigned k = threadIdx.x; k < n; k += BLOCK) {
+template <class SC, bool FINAL = false>
+__device__ __forceinline__ void flush_queue_sincos(Deferred& q, const typename SC::Tab& tab,
+                                                   float* os, float* oc, DevStats* st,
+                                                   long long elem_base) {
+  run_queue<FINAL>(q, st, [&](unsigned k) {
     AccResult2 a = SC::accurate(q.x[k], tab);
     os[q.idx[k]] = a.s;
     oc[q.idx[k]] = a.c;
-    if (!a.ok) {
-      atomicAdd(&q.esc, 1u);
-      note_escape(st, elem_base + q.idx[k]);
-    }
-  }
-  if (threadIdx.x == 0) {
-    q.lanes += n;
-    q.waves += (n + 63) / 64;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) q.n = 0;
-  __syncthreads();
+    if (!a.ok) note_escape(st, elem_base + q.idx[k]);
+  });
 }
 
 template <class SC>
@@ -530,7 +528,7 @@ __global__ void __launch_bounds__(BLOCK)
   SC::load(tab, threadIdx.x);
   if (threadIdx.x == 0) {
     q.n = 0;
-    q.lanes = q.waves = q.esc = 0;
+    q.lanes = q.waves = 0;
   }
   __syncthreads();
   const bool force = flags & CR_FLAG_FORCE_FALLBACK;
@@ -565,10 +563,7 @@ __global__ void __launch_bounds__(BLOCK)
               e[c] = a.s;
               ec[c] = a.c;
               atomicAdd(&q.lanes, 1u);
-              if (!a.ok) {
-                atomicAdd(&q.esc, 1u);
-                note_escape(st, elem_base + 4 * i + c);
-              }
+              if (!a.ok) note_escape(st, elem_base + 4 * i + c);
             }
           }
         }
@@ -592,14 +587,8 @@ __global__ void __launch_bounds__(BLOCK)
     }
   }
   __syncthreads();
-  if (q.n)
-    flush_queue_sincos<SC>(q, tab, reinterpret_cast<float*>(outs), reinterpret_cast<float*>(outc), st,
-                       elem_base);
-  if (threadIdx.x == 0 && q.lanes) {
-    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
-    atomicAdd(&c.fallback_lanes, (unsigned long long)q.lanes);
-    atomicAdd(&c.fallback_waves, (unsigned long long)q.waves);
-  }
+  flush_queue_sincos<SC, true>(q, tab, reinterpret_cast<float*>(outs),
+                               reinterpret_cast<float*>(outc), st, elem_base);
 }
 
 template <class SC>
@@ -658,30 +647,19 @@ struct OpLog64 {
 };
 
 struct Deferred64 {
-  unsigned n, lanes, waves, esc;
+  unsigned n, lanes, waves;
   unsigned idx[QCAP];
   double x[QCAP];
 };
 
-template <class Op>
-__device__ __noinline__ void flush_queue64(Deferred64& q, const typename Op::Tab& tab, double* out,
-                                           DevStats* st, long long elem_base) {
-  unsigned n = q.n < QCAP ? q.n : QCAP;
-  for (unsigned k = threadIdx.x; k < n; k += BLOCK) {
+template <class Op, bool FINAL = false>
+__device__ __forceinline__ void flush_queue64(Deferred64& q, const typename Op::Tab& tab,
+                                              double* out, DevStats* st, long long elem_base) {
+  run_queue<FINAL>(q, st, [&](unsigned k) {
     AccResultD a = Op::accurate(q.x[k], tab);
     out[q.idx[k]] = a.r;
-    if (!a.ok) {
-      atomicAdd(&q.esc, 1u);
-      note_escape(st, elem_base + q.idx[k]);
-    }
-  }
-  if (threadIdx.x == 0) {
-    q.lanes += n;
-    q.waves += (n + 63) / 64;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) q.n = 0;
-  __syncthreads();
+    if (!a.ok) note_escape(st, elem_base + q.idx[k]);
+  });
 }
 
 // The binary64 form of k_map_f32: tiles of 2048 doubles, four 128-bit
@@ -697,7 +675,7 @@ __global__ void __launch_bounds__(BLOCK)
   Op::load(tab, threadIdx.x);
   if (threadIdx.x == 0) {
     q.n = 0;
-    q.lanes = q.waves = q.esc = 0;
+    q.lanes = q.waves = 0;
   }
   __syncthreads();
   const bool force = flags & CR_FLAG_FORCE_FALLBACK;
@@ -731,10 +709,7 @@ __global__ void __launch_bounds__(BLOCK)
               AccResultD a = Op::accurate(x, tab);
               e[c] = a.r;
               atomicAdd(&q.lanes, 1u);
-              if (!a.ok) {
-                atomicAdd(&q.esc, 1u);
-                note_escape(st, elem_base + 2 * i + c);
-              }
+              if (!a.ok) note_escape(st, elem_base + 2 * i + c);
             }
           }
         }
@@ -753,12 +728,7 @@ __global__ void __launch_bounds__(BLOCK)
     }
   }
   __syncthreads();
-  if (q.n) flush_queue64<Op>(q, tab, outd, st, elem_base);
-  if (threadIdx.x == 0 && q.lanes) {
-    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
-    atomicAdd(&c.fallback_lanes, (unsigned long long)q.lanes);
-    atomicAdd(&c.fallback_waves, (unsigned long long)q.waves);
-  }
+  flush_queue64<Op, true>(q, tab, outd, st, elem_base);
 }
 
 template <class Op>
@@ -813,7 +783,7 @@ struct BTile {
 };
 
 struct BDeferred {
-  unsigned n, lanes, waves, esc;
+  unsigned n, lanes, waves;
   unsigned req[QCAP];
   unsigned idx[QCAP];
   float x[QCAP];
@@ -832,10 +802,7 @@ __device__ __forceinline__ void batch_enqueue(BDeferred& q, const typename Op::T
     AccResult a = Op::accurate(x, tab);
     res = a.r;
     atomicAdd(&q.lanes, 1u);
-    if (!a.ok) {
-      atomicAdd(&q.esc, 1u);
-      note_escape(st, (long long)idx);
-    }
+    if (!a.ok) note_escape(st, (long long)idx);
   }
 }
 
@@ -906,10 +873,7 @@ __device__ __forceinline__ void batch_tile_sincos(BReq R, BTile T, const typenam
         sv = a.s;
         c = a.c;
         atomicAdd(&q.lanes, 1u);
-        if (!a.ok) {
-          atomicAdd(&q.esc, 1u);
-          note_escape(st, (long long)(base + i));
-        }
+        if (!a.ok) note_escape(st, (long long)(base + i));
       }
     }
     os[i] = sv;
@@ -917,65 +881,29 @@ __device__ __forceinline__ void batch_tile_sincos(BReq R, BTile T, const typenam
   }
 }
 
-template <class Op>
-__device__ __forceinline__ void batch_flush_op(BDeferred& q, unsigned n, const typename Op::Tab& tab,
-                                               const BReq* reqs, DevStats* st) {
-  for (unsigned k = threadIdx.x; k < n; k += BLOCK) {
+// Run the accurate path on the queued elements (see run_queue).
+template <class Op, bool FINAL = false>
+__device__ __forceinline__ void batch_flush_one(BDeferred& q, const typename Op::Tab& tab,
+                                                const BReq* reqs, DevStats* st) {
+  run_queue<FINAL>(q, st, [&](unsigned k) {
     AccResult a = Op::accurate(q.x[k], tab);
     float* out = reinterpret_cast<float*>(reqs[q.req[k]].out);
     out[q.idx[k]] = a.r;
-    if (!a.ok) {
-      atomicAdd(&q.esc, 1u);
-      note_escape(st, (long long)q.idx[k]);
-    }
-  }
+    if (!a.ok) note_escape(st, (long long)q.idx[k]);
+  });
 }
 
-template <class SC>
-__device__ __forceinline__ void batch_flush_sincos(BDeferred& q, unsigned n,
-                                                   const typename SC::Tab& tab, const BReq* reqs,
-                                                   DevStats* st) {
-  for (unsigned k = threadIdx.x; k < n; k += BLOCK) {
+template <class SC, bool FINAL = false>
+__device__ __forceinline__ void batch_flush_one_sincos(BDeferred& q, const typename SC::Tab& tab,
+                                                       const BReq* reqs, DevStats* st) {
+  run_queue<FINAL>(q, st, [&](unsigned k) {
     AccResult2 a = SC::accurate(q.x[k], tab);
     const BReq& R = reqs[q.req[k]];
     float* out = reinterpret_cast<float*>(R.out);
     out[q.idx[k]] = a.s;
     out[R.n + q.idx[k]] = a.c;
-    if (!a.ok) {
-      atomicAdd(&q.esc, 1u);
-      note_escape(st, (long long)q.idx[k]);
-    }
-  }
-}
-
-// Run the accurate path on the queued elements, then empty the queue.  Called
-// by all threads of the workgroup.
-template <class Op>
-__device__ __noinline__ void batch_flush_one(BDeferred& q, const typename Op::Tab& tab,
-                                             const BReq* reqs, DevStats* st) {
-  unsigned n = q.n < QCAP ? q.n : QCAP;
-  batch_flush_op<Op>(q, n, tab, reqs, st);
-  if (threadIdx.x == 0) {
-    q.lanes += n;
-    q.waves += (n + 63) / 64;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) q.n = 0;
-  __syncthreads();
-}
-
-template <class SC>
-__device__ __noinline__ void batch_flush_one_sincos(BDeferred& q, const typename SC::Tab& tab,
-                                                    const BReq* reqs, DevStats* st) {
-  unsigned n = q.n < QCAP ? q.n : QCAP;
-  batch_flush_sincos<SC>(q, n, tab, reqs, st);
-  if (threadIdx.x == 0) {
-    q.lanes += n;
-    q.waves += (n + 63) / 64;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) q.n = 0;
-  __syncthreads();
+    if (!a.ok) note_escape(st, (long long)q.idx[k]);
+  });
 }
 
 // The batch runs one persistent kernel per function present (implementation
@@ -994,7 +922,7 @@ __global__ void __launch_bounds__(BLOCK)
   Op::load(tab, threadIdx.x);
   if (threadIdx.x == 0) {
     q.n = 0;
-    q.lanes = q.waves = q.esc = 0;
+    q.lanes = q.waves = 0;
   }
   __syncthreads();
   const bool force = flags & CR_FLAG_FORCE_FALLBACK;
@@ -1010,12 +938,7 @@ __global__ void __launch_bounds__(BLOCK)
     }
   }
   __syncthreads();
-  if (q.n) batch_flush_one<Op>(q, tab, reqs, st);
-  if (threadIdx.x == 0 && q.lanes) {
-    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
-    atomicAdd(&c.fallback_lanes, (unsigned long long)q.lanes);
-    atomicAdd(&c.fallback_waves, (unsigned long long)q.waves);
-  }
+  batch_flush_one<Op, true>(q, tab, reqs, st);
 }
 
 template <class SC>
@@ -1027,7 +950,7 @@ __global__ void __launch_bounds__(BLOCK)
   SC::load(tab, threadIdx.x);
   if (threadIdx.x == 0) {
     q.n = 0;
-    q.lanes = q.waves = q.esc = 0;
+    q.lanes = q.waves = 0;
   }
   __syncthreads();
   const bool force = flags & CR_FLAG_FORCE_FALLBACK;
@@ -1043,12 +966,7 @@ __global__ void __launch_bounds__(BLOCK)
     }
   }
   __syncthreads();
-  if (q.n) batch_flush_one_sincos<SC>(q, tab, reqs, st);
-  if (threadIdx.x == 0 && q.lanes) {
-    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
-    atomicAdd(&c.fallback_lanes, (unsigned long long)q.lanes);
-    atomicAdd(&c.fallback_waves, (unsigned long long)q.waves);
-  }
+  batch_flush_one_sincos<SC, true>(q, tab, reqs, st);
 }
 
 __global__ void k_zero_stats(DevStats* st) {
