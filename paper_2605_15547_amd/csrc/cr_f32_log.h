@@ -39,13 +39,21 @@ __device__ __forceinline__ void log_tab_load(LogTab& t, int tid) {
   }
 }
 
-// Fast-path error: Q approximation < 2^-57.6 |t| (|t| <= 1/16); the inner sum
-// (|K t + ...| < 0.1) carries one rounding each for t Q and the additions
-// (< 2^-56 absolute); the last addition 1/2 ulp.  |y| >= 0.0128 except on the
-// two sub-intervals around 1, where y = K t + t Q(t) (K >= 0.434) has relative
-// error < 2^-51.7.  That is below 2.5 ulps; the test uses 8 (2^3) to absorb the
-// binade of the computed value.
-constexpr int LOG_LOG2E = 3;
+// Fast-path error (t and K t are exact: t is a multiple of 2^-33 below 1/16,
+// K has 20 bits).  Q's approximation error (below 2^-57.6) and its Horner
+// evaluation error (below 2^-52 |Q|, |Q| < 0.05) enter through t Q, which is
+// rounded once inside inner (< 2^-53 |t Q|); s = K t + inner is rounded once
+// (half an ulp of s, at most 2^-57) and yh = A.hi + s once more (half an ulp
+// of y).  Summed per interval of the reduction, for e' = 0 (where |y| can be
+// as small as 0.0128 while |s| is not) and e' != 0, over a fine grid of each
+// interval and the three bases, the total stays below 0.82 ulp of y.  A y just
+// above a power of two may give a yh just below it, whose ulp is half as large:
+// the bound is 1.64 ulps of yh, and the test uses 2 (2^1).  Every binary32
+// input is checked against the accurate path on the GPU.
+// log1p adds the rounding of its correction term (for |x| > 1 it moves y by
+// up to 2^-52 relative): its test uses 8 (2^3).
+constexpr int LOG_LOG2E = 1;
+constexpr int LOG1P_LOG2E = 3;
 
 template <int K>
 __device__ __forceinline__ double log_C_hi() {
@@ -158,7 +166,9 @@ __device__ __forceinline__ float log_fast(float xf, const LogTab& tb, bool& ok) 
   dd A = fast_two_sum(ed * log_C_hi<K>(), S.L.x);  // |e' C| >= |L| unless e' = 0
   double inner = fma(t, Q, A.lo + fma(ed, log_C_lo<K>(), S.L.y));
   double yh = A.hi + fma(log_K<K>(), t, inner);
-  float res = round_f32_fast<LOG_LOG2E>(yh, ok);
+  // logf, log2f and log10f round to normal binary32 numbers (or to +0 at 1)
+  float res = K == LOGK_1P ? round_f32_fast<LOG1P_LOG2E>(yh, ok)
+                           : round_f32_bits<LOG_LOG2E>(yh, ok);
   float sp;
   if (log_special<K>(xf, sp)) {
     res = sp;

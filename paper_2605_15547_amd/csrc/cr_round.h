@@ -57,6 +57,20 @@ __device__ __forceinline__ float round_f32_fast(double yh, bool& ok) {
   return b;
 }
 
+// The same test read off the bits of yh, for results that round to a normal
+// binary32 number or to zero (|yh| in [2^-126, 2^128), or yh = 0): within the
+// binade of yh the binary32 rounding boundaries -- the midpoints between
+// consecutive floats -- are exactly the binary64 numbers whose 29 low
+// significand bits equal 2^28, and a binade edge is a float, not a boundary.
+// So no boundary lies within 2^LOG2E ulps of yh exactly when those 29 bits
+// differ from 2^28 by more than 2^LOG2E.
+template <int LOG2E>
+__device__ __forceinline__ float round_f32_bits(double yh, bool& ok) {
+  const uint32_t lo = (uint32_t)__double2loint(yh);
+  ok = ((lo - (0x10000000u - (1u << LOG2E))) & 0x1fffffffu) > (2u << LOG2E);
+  return (float)yh;
+}
+
 // Same, with an absolute error bound instead of a count of ulps.
 __device__ __forceinline__ float round_f32_fast_abs(double yh, double err, bool& ok) {
   float a = (float)(yh - err);
