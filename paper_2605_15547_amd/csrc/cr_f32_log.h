@@ -50,10 +50,12 @@ __device__ __forceinline__ void log_tab_load(LogTab& t, int tid) {
 // above a power of two may give a yh just below it, whose ulp is half as large:
 // the bound is 1.64 ulps of yh, and the test uses 2 (2^1).  Every binary32
 // input is checked against the accurate path on the GPU.
-// log1p adds the rounding of its correction term (for |x| > 1 it moves y by
-// up to 2^-52 relative): its test uses 8 (2^3).
+// log1p adds the rounding of t's correction term (a relative 2^-53 of t, at
+// most half an ulp of y near x = 0, where y ~ t); 1 + x is exact for
+// x < 2^29, and beyond, where y > 20, the inexact correction moves y by far
+// less than its ulp: 1.32 ulps of y, 2.7 of yh; its test uses 4 (2^2).
 constexpr int LOG_LOG2E = 1;
-constexpr int LOG1P_LOG2E = 3;
+constexpr int LOG1P_LOG2E = 2;
 
 template <int K>
 __device__ __forceinline__ double log_C_hi() {
@@ -166,9 +168,10 @@ __device__ __forceinline__ float log_fast(float xf, const LogTab& tb, bool& ok) 
   dd A = fast_two_sum(ed * log_C_hi<K>(), S.L.x);  // |e' C| >= |L| unless e' = 0
   double inner = fma(t, Q, A.lo + fma(ed, log_C_lo<K>(), S.L.y));
   double yh = A.hi + fma(log_K<K>(), t, inner);
-  // logf, log2f and log10f round to normal binary32 numbers (or to +0 at 1)
-  float res = K == LOGK_1P ? round_f32_fast<LOG1P_LOG2E>(yh, ok)
-                           : round_f32_bits<LOG_LOG2E>(yh, ok);
+  // logf, log2f and log10f round to normal binary32 numbers (or to +0 at 1),
+  // log1pf too except for subnormal x, which are left to the accurate path
+  float res = round_f32_bits<K == LOGK_1P ? LOG1P_LOG2E : LOG_LOG2E>(yh, ok);
+  if (K == LOGK_1P) ok = ok && fabs(yh) >= 0x1p-126;
   float sp;
   if (log_special<K>(xf, sp)) {
     res = sp;
