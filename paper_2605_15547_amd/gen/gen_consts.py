@@ -168,6 +168,12 @@ def gen_exp():
     h, l = dd(16 * mp.log(10) / ln2)
     emit_const("LOG2_10_16_HI", h, "16 log2(10) hi")
     emit_const("LOG2_10_16_LO", l, "16 log2(10) lo")
+    # exp10f fast reduction: C = 16 log2(10) = C1 + C2 with C1 on 28 bits, so
+    # that x C1 is exact for binary32 x; C2 enters pre-multiplied by ln2/16
+    c = 16 * mp.log(10) / ln2
+    c1 = split_bits(c, 28)
+    emit_const("LOG2_10_16_C1", c1, "16 log2(10) rounded to 28 bits")
+    emit_const("EXP10_C2_LN2_16", d((c - mp.mpf(c1)) * ln2 / 16), "(16 log2(10) - C1) ln2/16")
     h, l = dd(mp.log(10))
     emit_const("LN10_HI", h, "ln 10 hi")
     emit_const("LN10_LO", l, "ln 10 lo")
