@@ -10,10 +10,11 @@
 // with K = 1/ln b on 20 bits (K t exact) and Q a minimax polynomial on
 // t in [-1/32, 1/16].  c_j = 1 on the two sub-intervals next to 1, so for x
 // near 1 the result is K t + t Q(t) with no cancellation.  log1pf reduces
-// u = RN(1 + x) the same way and moves the rounding error of u (exact by
-// Fast2Sum for |x| <= 1) into t: t = m c_j - 1 + (1 + x - u) c_j 2^-e'.  Near
-// x = 0 this gives c_j = 1, e' = 0 and t = x exactly; for |x| > 1 the term is
-// below 2^-53 of u and only approximate, which moves log(u) by < 2^-52.
+// u = RN(1 + x) the same way.  1 + x is exact for binary32 x unless |x| < 2^-29
+// or x >= 2^29.  For |x| < 2^-29, u is within 2^-29 of 1, so e' = 0 and c_j = 1,
+// and the fast path takes t = x exactly; for x >= 2^29, log(u) differs from
+// log(1 + x) by less than 2^-53 while the result exceeds 20 (ulp 2^-48).  The
+// accurate path adds the rounding error of u, scaled like m, to t instead.
 //
 // The binary64 fast path ends with the rounding test of cr_round.h; lanes that
 // fail it run the accurate double-double path below (log1p(t) = 2 atanh(t/(2+t))
@@ -50,12 +51,10 @@ __device__ __forceinline__ void log_tab_load(LogTab& t, int tid) {
 // above a power of two may give a yh just below it, whose ulp is half as large:
 // the bound is 1.64 ulps of yh, and the test uses 2 (2^1).  Every binary32
 // input is checked against the accurate path on the GPU.
-// log1p adds the rounding of t's correction term (a relative 2^-53 of t, at
-// most half an ulp of y near x = 0, where y ~ t); 1 + x is exact for
-// x < 2^29, and beyond, where y > 20, the inexact correction moves y by far
-// less than its ulp: 1.32 ulps of y, 2.7 of yh; its test uses 4 (2^2).
+// log1p adds, for x >= 2^29, the rounding of 1 + x (below 2^-53 absolute on
+// y > 20: a thirtieth of an ulp): 0.85 ulp of y, 1.7 of yh; its test also
+// uses 2.
 constexpr int LOG_LOG2E = 1;
-constexpr int LOG1P_LOG2E = 2;
 
 template <int K>
 __device__ __forceinline__ double log_C_hi() {
@@ -134,11 +133,7 @@ __device__ __forceinline__ LogSetup log_setup(float xf, const LogTab& tb) {
   S.c = tb.c[j];
   S.L = tb.L[j];
   S.t = fma(S.m, S.c, -1.0);
-  if (K == LOGK_1P) {
-    // the rounding error of u = 1 + x, scaled like m (Fast2Sum, |x| <= 1)
-    const double ulo = (x - (S.u - 1.0)) * pow2i(-S.e2);
-    S.t = fma(ulo, S.c, S.t);
-  }
+  if (K == LOGK_1P) S.t = fabsf(xf) < 0x1p-29f ? x : S.t;  // 1 + x inexact: t = x
   return S;
 }
 
@@ -170,7 +165,7 @@ __device__ __forceinline__ float log_fast(float xf, const LogTab& tb, bool& ok) 
   double yh = A.hi + fma(log_K<K>(), t, inner);
   // logf, log2f and log10f round to normal binary32 numbers (or to +0 at 1),
   // log1pf too except for subnormal x, which are left to the accurate path
-  float res = round_f32_bits<K == LOGK_1P ? LOG1P_LOG2E : LOG_LOG2E>(yh, ok);
+  float res = round_f32_bits<LOG_LOG2E>(yh, ok);
   if (K == LOGK_1P) ok = ok && fabs(yh) >= 0x1p-126;
   float sp;
   if (log_special<K>(xf, sp)) {
