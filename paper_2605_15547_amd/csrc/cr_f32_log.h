@@ -17,8 +17,8 @@
 // accurate path adds the rounding error of u, scaled like m, to t instead.
 //
 // The binary64 fast path ends with the rounding test of cr_round.h; lanes that
-// fail it run the accurate double-double path below (log1p(t) = 2 atanh(t/(2+t))
-// by its series), as in the exponential family.
+// fail it run the accurate double-double path below (the log1p series to degree
+// 17 on the exact double-double t), as in the exponential family.
 #pragma once
 #include "cr_consts.h"
 #include "cr_round.h"
@@ -88,27 +88,23 @@ __device__ __forceinline__ double log_Q(double t) {
   }
 }
 
-// log1p(t) for a double-double t with |t| <= 1/16: 2 atanh(s), s = t/(2+t),
-// series in s^2 (terms of index >= 6 in binary64, the rest in double-double).
-__device__ __forceinline__ dd log1p_dd(dd t) {
-  dd den = dd_add_d(t, 2.0);
-  double q1 = t.hi / den.hi;
-  dd pr = dd_mul_d(den, q1);
-  dd r = dd_add(t, dd_neg(pr));
-  double q2 = r.hi / den.hi;
-  dd s = fast_two_sum(q1, q2);
-  dd s2 = dd_mul(s, s);
-  double ph = INV_ODD[ATANH_N].x;
+// log1p(t) for the accurate path of the binary32 functions: a double-double
+// t with |t| <= 1/16, to within 2^-69.9 |t|.  The series to degree 17
+// (remainder below 2^-72.2 |t|) as t (1 + t (-1/2 + t (1/3 + t (-1/4 +
+// t R(t))))), with R = sum over n = 5..17 of (-1)^(n+1) t^(n-5) / n in
+// binary64 (its rounding, below 2^-54.3, is multiplied by |t|^4 <= 2^-16) and
+// the four outer steps in double-double.
+__device__ __forceinline__ dd log1p_dd_short(dd t) {
+  double R = 1.0 / 17;
 #pragma unroll
-  for (int k = ATANH_N - 1; k >= 6; k--) ph = fma(ph, s2.hi, INV_ODD[k].x);
-  dd p = {ph, 0.0};
-#pragma unroll
-  for (int k = 5; k >= 0; k--) {
-    double2 c = INV_ODD[k];
-    p = dd_add(dd_mul(p, s2), dd{c.x, c.y});
-  }
-  dd y = dd_mul(p, s);
-  return {2.0 * y.hi, 2.0 * y.lo};
+  for (int n = 16; n >= 5; n--) R = fma(R, t.hi, (n & 1 ? 1.0 : -1.0) / n);
+  dd w = two_prod(t.hi, R);
+  w.lo = fma(t.lo, R, w.lo);
+  w = dd_add_ord(dd{-0.25, 0.0}, w);  // |t R| < 1/64
+  w = dd_add_ord(dd{THIRD_HI, THIRD_LO}, dd_mul(t, w));
+  w = dd_add_ord(dd{-0.5, 0.0}, dd_mul(t, w));
+  w = dd_add_ord(dd{1.0, 0.0}, dd_mul(t, w));
+  return dd_mul(t, w);
 }
 
 // Shared set-up: u (= x, or 1 + x for log1pf), the decomposition u = 2^e' m
@@ -190,15 +186,19 @@ __device__ __noinline__ AccResult log_accurate(float xf, const LogTab& tb) {
     const double ulo = two_sum(1.0, (double)xf).lo * pow2i(-S.e2);
     t = dd_add_d(t, ulo * S.c);
   }
-  dd l = log1p_dd(t);
+  dd l = log1p_dd_short(t);
   if (K == LOGK_2) l = dd_mul(l, dd{INV_LN2_HI, INV_LN2_LO});
   if (K == LOGK_10) l = dd_mul(l, dd{INV_LN10_HI, INV_LN10_LO});
   dd C = K == LOGK_2 ? dd{1.0, 0.0}
                      : K == LOGK_10 ? dd{LOG10_2_HI, LOG10_2_LO} : dd{LN2_HI, LN2_LO};
   dd y = dd_add(dd_mul_d(C, (double)S.e2), dd{S.L.x, S.L.y});
   y = dd_add(y, l);
+  // log1p(t) is within 2^-69.9 |t|, and |t| <= 4.9 |y| (|y| >= 0.0128 unless
+  // e' = 0 and c_j = 1, where y is log1p(t) / ln b): y is within 2^-67.5 of
+  // its value relative, below the 2^-66.8 that separates the hardest binary32
+  // case from a rounding boundary (log1pf, at 2^-42.8 ulp)
   bool ok;
-  float r = round_f32_dd(y.hi, y.lo, 0x1p-85, ok);
+  float r = round_f32_dd(y.hi, y.lo, 0x1p-67, ok);
   return {r, ok ? 1 : 0};
 }
 

@@ -279,10 +279,6 @@ def gen_log():
     h, l = dd(mp.log10(2))
     emit_const("LOG10_2_HI", h)
     emit_const("LOG10_2_LO", l)
-    # 2 atanh(s) = 2 sum s^(2k+1)/(2k+1), |s| <= 0.0304: 12 terms leave < 2^-120
-    N = 12
-    emit("#define ATANH_N %d" % N)
-    emit_dd_table("INV_ODD", [mp.mpf(1) / (2 * k + 1) for k in range(N + 1)], "1/(2k+1)")
     emit()
 
 
