@@ -150,6 +150,19 @@ __device__ __forceinline__ bool log_special(float xf, float& res) {
   return nan | zero1p | dom | inf;
 }
 
+// The fast path's special cases for logf, log2f and log10f, in fewer
+// operations: one class test picks the inputs that are not positive finite
+// (NaN, infinities, zeros, negatives), and the hardware base-2 logarithm gives
+// their results (measured on gfx950: -inf at +-0, +inf at +inf, a NaN quieted
+// with its payload and sign) except for negative inputs, where it returns the
+// negative default NaN and the positive one is wanted.  The accurate path keeps
+// log_special; the exhaustive test compares both on every encoding.
+__device__ __forceinline__ bool log_special_fast(float xf, float& res) {
+  const float h = __builtin_amdgcn_logf(xf);
+  res = xf < 0.0f ? bits_f32(0x7fc00000u) : h;
+  return __builtin_amdgcn_class(xf, 0x27f);  // all classes but +denormal, +normal
+}
+
 template <int K>
 __device__ __forceinline__ float log_fast(float xf, const LogTab& tb, bool& ok) {
   LogSetup S = log_setup<K>(xf, tb);
@@ -164,7 +177,7 @@ __device__ __forceinline__ float log_fast(float xf, const LogTab& tb, bool& ok) 
   float res = round_f32_bits<LOG_LOG2E>(yh, ok);
   if (K == LOGK_1P) ok = ok && fabs(yh) >= 0x1p-126;
   float sp;
-  if (log_special<K>(xf, sp)) {
+  if (K == LOGK_1P ? log_special<K>(xf, sp) : log_special_fast(xf, sp)) {
     res = sp;
     ok = true;
   }
