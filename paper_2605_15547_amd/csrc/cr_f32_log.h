@@ -27,16 +27,23 @@ namespace cr {
 
 enum { LOGK_E = 0, LOGK_2 = 1, LOGK_10 = 2, LOGK_1P = 3 };
 
+// One 32-byte row per sub-interval, so that both reads of a lookup share one
+// address (j 32) and differ only in their immediate offsets.
+struct LogRow {
+  double2 L;  // -log_b(c_j), double-double
+  double c;   // c_j
+  double pad;
+};
 struct LogTab {
-  double c[16];
-  double2 L[16];
+  LogRow row[16];
 };
 
 template <int K>
 __device__ __forceinline__ void log_tab_load(LogTab& t, int tid) {
   if (tid < 16) {
-    t.c[tid] = LOG_C[tid];
-    t.L[tid] = (K == LOGK_2) ? LOG2_L[tid] : (K == LOGK_10) ? LOG10_L[tid] : LOGE_L[tid];
+    t.row[tid].L = (K == LOGK_2) ? LOG2_L[tid] : (K == LOGK_10) ? LOG10_L[tid] : LOGE_L[tid];
+    t.row[tid].c = LOG_C[tid];
+    t.row[tid].pad = 0.0;
   }
 }
 
@@ -126,8 +133,8 @@ __device__ __forceinline__ LogSetup log_setup(float xf, const LogTab& tb) {
   int fold = j >> 3;
   S.e2 = ((hi >> 20) & 0x7ff) - 1023 + fold;
   S.m = __hiloint2double((hi & 0x000fffff) | ((1023 - fold) << 20), __double2loint(S.u));
-  S.c = tb.c[j];
-  S.L = tb.L[j];
+  S.c = tb.row[j].c;
+  S.L = tb.row[j].L;
   S.t = fma(S.m, S.c, -1.0);
   if (K == LOGK_1P) S.t = fabsf(xf) < 0x1p-29f ? x : S.t;  // 1 + x inexact: t = x
   return S;
