@@ -15,7 +15,10 @@
 //   same 16-entry 9-bit reciprocal table as binary32: t = m c_j - 1 exact as a
 //   double-double (TwoProd), log x = e' ln2 - ln c_j + log1p(t) with
 //   log1p t = t - t^2/2 + t^3/3 + t^4 S(t) (main path) or 2 atanh(t/(2+t))
-//   (accurate path, triple-double).
+//   (accurate path).
+// The accurate path first tries a double-double middle path, which decides
+// all but the inputs within about 2^-42 ulp of a rounding boundary, and only
+// those take the triple-double evaluation.
 #pragma once
 #include "cr_consts.h"
 #include "cr_round.h"
@@ -56,6 +59,22 @@ __device__ __forceinline__ bool exp64_special(double x, double& res) {
 // the test uses 2^-66 |y| (relative)
 constexpr double EXP64_EPS = 0x1p-66;
 
+// 2^m y rounded to binary64 from the double-double y (in [2^-1/512, 2)) known
+// to within e; ok when every value in y +- e rounds the same way.
+__device__ __forceinline__ double exp64_round(dd y, int m, double e, bool& ok) {
+  if (m >= -1021) {  // normal result: round in the unscaled domain, then scale
+    double a = y.hi + (y.lo - e);
+    double b = y.hi + (y.lo + e);
+    ok = a == b;
+    return scale_pow2(b, m);
+  }
+  // subnormal (or zero) result: round y 2^(m+1074) to an integer
+  // (y 2^(m+1074) < 2^53; for m + 1074 < 0 it is below 1 and rounds to 0 or 1)
+  double sc = pow2i(m + 1074 > -200 ? m + 1074 : -200);
+  double n = round_to_int(y.hi * sc, y.lo * sc, 0.0, e * sc, ok);
+  return n * 0x1p-1074;
+}
+
 __device__ __forceinline__ double exp64_fast(double x, const Exp64Tab& tb, bool& ok) {
   double xc = fmin(fmax(x, -746.0), 710.0);  // beyond: 0 or +inf after scaling
   double kd = rint(xc * EXP64_INV);
@@ -72,19 +91,7 @@ __device__ __forceinline__ double exp64_fast(double x, const Exp64Tab& tb, bool&
   double4 A = tb.t1[(k >> 4) & 15], B = tb.t2[k & 15];
   dd T = dd_mul(dd{A.x, A.y}, dd{B.x, B.y});
   dd y = dd_add_ord(T, dd_mul(T, q));  // T e^r, in [2^-1/512, 2); |T q| < 2^-9 |T|
-  double res;
-  double e = fabs(y.hi) * EXP64_EPS;
-  if (m >= -1021) {  // normal result: round in the unscaled domain, then scale
-    double a = y.hi + (y.lo - e);
-    double b = y.hi + (y.lo + e);
-    ok = a == b;
-    res = scale_pow2(b, m);
-  } else {  // subnormal (or zero) result: round y 2^(m+1074) to an integer
-    // (y 2^(m+1074) < 2^53; for m + 1074 < 0 it is below 1 and rounds to 0 or 1)
-    double sc = pow2i(m + 1074 > -200 ? m + 1074 : -200);
-    double n = round_to_int(y.hi * sc, y.lo * sc, 0.0, e * sc, ok);
-    res = n * 0x1p-1074;
-  }
+  double res = exp64_round(y, m, fabs(y.hi) * EXP64_EPS, ok);
   double sp;
   if (exp64_special(x, sp)) {
     res = sp;
@@ -98,9 +105,42 @@ struct AccResultD {
   int ok;
 };
 
+// Middle path (double-double), tried first by the accurate path: the main
+// path's reduction (r within 2^-110) and tables (2^-104), with e^r to about
+// 2^-104 relative: the Taylor series to degree 9 (remainder below 2^-116), its
+// degrees 5..9 in binary64 as r P(r) inside the innermost step (rounding below
+// 2^-107 of the result) and degrees 0..4 by double-double Horner steps.
+// y = T e^r is within 2^-100 of e^x relative; the test allows 2^-95, so only
+// inputs within about 2^-42 ulp of a rounding boundary go on to the
+// triple-double path.
+__device__ __forceinline__ double exp64_mid(double x, const Exp64Tab& tb, bool& ok) {
+  double xc = fmin(fmax(x, -746.0), 710.0);
+  double kd = rint(xc * EXP64_INV);
+  int k = (int)kd;
+  double r0 = fma(-kd, EXP64_C1, xc);
+  dd p = two_prod(kd, EXP64_C2);
+  dd s = two_sum(r0, -p.hi);
+  dd r = fast_two_sum(s.hi, (s.lo - p.lo) - kd * EXP64_C3);
+  double P = INV_FACT[9].x;
+#pragma unroll
+  for (int i = 8; i >= 5; i--) P = fma(P, r.hi, INV_FACT[i].x);
+  dd w = dd_add_ord(dd{INV_FACT[4].x, INV_FACT[4].y}, dd{r.hi * P, 0.0});
+#pragma unroll
+  for (int i = 3; i >= 0; i--) w = dd_add_ord(dd{INV_FACT[i].x, INV_FACT[i].y}, dd_mul(r, w));
+  int m = k >> 8;  // w = e^r
+  double4 A = tb.t1[(k >> 4) & 15], B = tb.t2[k & 15];
+  dd T = dd_mul(dd{A.x, A.y}, dd{B.x, B.y});
+  dd y = dd_mul(T, w);
+  return exp64_round(y, m, fabs(y.hi) * 0x1p-95, ok);
+}
+
 __device__ __noinline__ AccResultD exp64_accurate(double x, const Exp64Tab& tb) {
   double sp;
   if (exp64_special(x, sp)) return {sp, 1};
+  bool mid_ok;
+  const double rm = exp64_mid(x, tb, mid_ok);
+  if (mid_ok) return {rm, 1};
+  // triple-double path
   double xc = fmin(fmax(x, -746.0), 710.0);
   double kd = rint(xc * EXP64_INV);
   int k = (int)kd;
@@ -206,9 +246,49 @@ __device__ __forceinline__ double log64_fast(double x, const Log64Tab& tb, bool&
   return res;
 }
 
+// Middle path (double-double), tried first by the accurate path: t = m c - 1
+// exact as in the main path, s = t/(2 + t) in double-double (two divisions,
+// |s| < 1/31), log1p t = 2 atanh(s) by its series to s^21 (remainder below
+// 2^-105 relative), terms 6..10 in binary64 (rounding below 2^-107) and 0..5
+// by double-double Horner steps in s^2; then e' ln2 + (-log c_j) + log1p t in
+// double-double (ln2 and the table to 2^-106).  y is within 2^-100 of log x
+// relative (|y| >= 0.03 unless e' = 0 and c_j = 1, where y = log1p t); the
+// test allows 2^-95.
+__device__ __forceinline__ double log64_mid(double x, const Log64Tab& tb, bool& ok) {
+  Log64Setup S = log64_setup(x);
+  double c = tb.c[S.j];
+  double4 L = tb.L[S.j];
+  dd p = two_prod(S.m, c);
+  dd t = fast_two_sum(p.hi - 1.0, p.lo);
+  dd den = dd_add_d(t, 2.0);
+  double q1 = t.hi / den.hi;
+  dd rr = dd_add(t, dd_neg(dd_mul_d(den, q1)));  // t - q1 (2 + t)
+  dd s = fast_two_sum(q1, rr.hi / den.hi);
+  dd s2 = dd_mul(s, s);
+  double P = INV_ODD_DD[10].x;
+#pragma unroll
+  for (int k = 9; k >= 6; k--) P = fma(P, s2.hi, INV_ODD_DD[k].x);
+  dd w = {P, 0.0};
+#pragma unroll
+  for (int k = 5; k >= 0; k--) w = dd_add_ord(dd{INV_ODD_DD[k].x, INV_ODD_DD[k].y}, dd_mul(s2, w));
+  dd l = dd_mul(s, w);
+  l = {2.0 * l.hi, 2.0 * l.lo};
+  dd el = dd_mul_d(dd{LN2_TD[0].x, LN2_TD[0].y}, (double)S.e2);
+  dd y = dd_add(dd_add(el, dd{L.x, L.y}), l);
+  double e = fabs(y.hi) * 0x1p-95;
+  double a = y.hi + (y.lo - e);
+  double b = y.hi + (y.lo + e);
+  ok = a == b;
+  return b;
+}
+
 __device__ __noinline__ AccResultD log64_accurate(double x, const Log64Tab& tb) {
   double sp;
   if (log64_special(x, sp)) return {sp, 1};
+  bool mid_ok;
+  const double rm = log64_mid(x, tb, mid_ok);
+  if (mid_ok) return {rm, 1};
+  // triple-double path
   Log64Setup S = log64_setup(x);
   double c = tb.c[S.j];
   dd p = two_prod(S.m, c);
