@@ -55,9 +55,13 @@ __device__ __forceinline__ bool exp64_special(double x, double& res) {
   return nan | (x == 0.0);
 }
 
-// main-path error: q within 2^-71, tables 2^-104, products and sum 2^-104:
-// the test uses 2^-66 |y| (relative)
-constexpr double EXP64_EPS = 0x1p-66;
+// main-path error, |r| <= 2^-9.53: q = e^r - 1 carries the roundings of
+// r.hi^2 (2^-73.1 after the factor P ~ 1/2), of the fma (2^-73.1), P's
+// evaluation error times r^2 (2^-73), the r.lo term left out of r^2 (2^-72)
+// and P's approximation error (2^-83.9): below 2^-70.7 in all; T (2^-104) and
+// the double-double products and sum (2^-103) add nothing visible.  Relative
+// to y >= T (1 - 2^-9.5) that is 2^-70.7; the test uses 2^-69 |y|.
+constexpr double EXP64_EPS = 0x1p-69;
 
 // 2^m y rounded to binary64 from the double-double y (in [2^-1/512, 2)) known
 // to within e; ok when every value in y +- e rounds the same way.
