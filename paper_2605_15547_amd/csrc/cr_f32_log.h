@@ -170,6 +170,16 @@ __device__ __forceinline__ bool log_special_fast(float xf, float& res) {
   return __builtin_amdgcn_class(xf, 0x27f);  // all classes but +denormal, +normal
 }
 
+// The same for log1pf, through the hardware logarithm of 1 + x (binary32):
+// NaN (1 + x keeps the payload and quiets it), x = -1 (-inf) and +inf come out
+// right; x < -1 needs the positive default NaN and x = +-0 the signed zero.
+__device__ __forceinline__ bool log1p_special_fast(float xf, float& res) {
+  const float h = __builtin_amdgcn_logf(1.0f + xf);
+  res = xf < -1.0f ? bits_f32(0x7fc00000u) : (xf == 0.0f ? xf : h);
+  // NaN, infinities, zeros (class mask), and everything at or below -1
+  return __builtin_amdgcn_class(xf, 0x267) | (xf <= -1.0f);
+}
+
 template <int K>
 __device__ __forceinline__ float log_fast(float xf, const LogTab& tb, bool& ok) {
   LogSetup S = log_setup<K>(xf, tb);
@@ -184,7 +194,7 @@ __device__ __forceinline__ float log_fast(float xf, const LogTab& tb, bool& ok) 
   float res = round_f32_bits<LOG_LOG2E>(yh, ok);
   if (K == LOGK_1P) ok = ok && fabs(yh) >= 0x1p-126;
   float sp;
-  if (K == LOGK_1P ? log_special<K>(xf, sp) : log_special_fast(xf, sp)) {
+  if (K == LOGK_1P ? log1p_special_fast(xf, sp) : log_special_fast(xf, sp)) {
     res = sp;
     ok = true;
   }
