@@ -56,12 +56,12 @@ __device__ __forceinline__ void log_tab_load(LogTab& t, int tid) {
 // as small as 0.0128 while |s| is not) and e' != 0, over a fine grid of each
 // interval and the three bases, the total stays below 0.82 ulp of y.  A y just
 // above a power of two may give a yh just below it, whose ulp is half as large:
-// the bound is 1.64 ulps of yh, and the test uses 2 (2^1).  Every binary32
-// input is checked against the accurate path on the GPU.
-// log1p adds, for x >= 2^29, the rounding of 1 + x (below 2^-53 absolute on
-// y > 20: a thirtieth of an ulp): 0.85 ulp of y, 1.7 of yh; its test also
-// uses 2.
-constexpr int LOG_LOG2E = 1;
+// the bound is 1.64 ulps of yh.  log1p adds, for x >= 2^29, the rounding of
+// 1 + x (below 2^-53 absolute on y > 20: a thirtieth of an ulp): 0.85 ulp of
+// y, 1.7 of yh.  Both are below 2, so the bit test rejects yh only when its low
+// bits lie within 1 of the boundary pattern (E = 1).  Every binary32 input is
+// checked against the accurate path on the GPU.
+constexpr unsigned LOG_TEST_E = 1;
 
 template <int K>
 __device__ __forceinline__ double log_C_hi() {
@@ -191,7 +191,7 @@ __device__ __forceinline__ float log_fast(float xf, const LogTab& tb, bool& ok) 
   double yh = A.hi + fma(log_K<K>(), t, inner);
   // logf, log2f and log10f round to normal binary32 numbers (or to +0 at 1),
   // log1pf too except for subnormal x, which are left to the accurate path
-  float res = round_f32_bits<LOG_LOG2E>(yh, ok);
+  float res = round_f32_bits<LOG_TEST_E>(yh, ok);
   if (K == LOGK_1P) ok = ok && fabs(yh) >= 0x1p-126;
   float sp;
   if (K == LOGK_1P ? log1p_special_fast(xf, sp) : log_special_fast(xf, sp)) {

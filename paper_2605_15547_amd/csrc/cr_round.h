@@ -62,12 +62,13 @@ __device__ __forceinline__ float round_f32_fast(double yh, bool& ok) {
 // binade of yh the binary32 rounding boundaries -- the midpoints between
 // consecutive floats -- are exactly the binary64 numbers whose 29 low
 // significand bits equal 2^28, and a binade edge is a float, not a boundary.
-// So no boundary lies within 2^LOG2E ulps of yh exactly when those 29 bits
-// differ from 2^28 by more than 2^LOG2E.
-template <int LOG2E>
+// Those bits and 2^28 are integers (in ulps of yh), so when they differ by
+// more than E no boundary lies within E + 1 ulps of yh: the test is sound for
+// an error bound below E + 1 ulps.
+template <unsigned E>
 __device__ __forceinline__ float round_f32_bits(double yh, bool& ok) {
   const uint32_t lo = (uint32_t)__double2loint(yh);
-  ok = ((lo - (0x10000000u - (1u << LOG2E))) & 0x1fffffffu) > (2u << LOG2E);
+  ok = ((lo - (0x10000000u - E)) & 0x1fffffffu) > 2u * E;
   return (float)yh;
 }
 
