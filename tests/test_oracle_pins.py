@@ -9,6 +9,7 @@ the accuracy each function needs.
 """
 import json
 import os
+import zlib
 
 import numpy as np
 import pytest
@@ -103,7 +104,7 @@ def sample(func, n, seed):
 @pytest.mark.parametrize("func", F32 + ["exp", "log"])
 def test_brute_force_vs_mpmath(oracle, func):
     """Random inputs across the whole domain: oracle == mpmath (400 bits)."""
-    x = sample(func, 160, 11 + (hash(func) % 1000))
+    x = sample(func, 160, 11 + (zlib.crc32(func.encode()) % 1000))
     got = oracle.evaluate(func, x)
     for xi, gi in zip(x, got):
         ref = mp_ref(func, xi)
