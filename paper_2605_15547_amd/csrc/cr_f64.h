@@ -211,9 +211,24 @@ __device__ __forceinline__ Log64Setup log64_setup(double x) {
   return S;
 }
 
-// main-path error: below 2^-71 absolute with |y| >= 2^-5 (or a relative
-// 2^-104 when y = log1p t alone): the test uses 2^-65 |y|
-constexpr double LOG64_EPS = 0x1p-65;
+// Main-path error, split by where it arises:
+//  * tail = t2.hi^2 sp stands for t^4 S(t): t2.hi carries t^2 within 3u
+//    (u = 2^-53; within u when c_j = 1, where t.lo = 0), the square, the
+//    Horner evaluation of S at t.hi (at most 1.2u relative: s0 = -1/4
+//    dominates, |s1 t / s0| < 0.06) and the product each one more rounding:
+//    below 9.2u = 2^-49.8 of |tail| in all.  S's own fit error is at most
+//    t^4 sup|g - S| (g the exact quotient; below 2^-57 t^4, checked in the
+//    bound tests) = 2^-55 of |tail|, and adding tail to b3.lo one more u of
+//    it.  LOG64_TAIL_EPS = 2^-49 covers the sum with a factor 1.6 to spare.
+//  * the rest: t, t^2/2 and t^3/3 in double-double (relative 2^-100), the
+//    table -ln c_j and e' ln2 to 2^-106, the double-double sums (2^-101):
+//    below 2^-99 |y|, where LOG64_EPS = 2^-70 leaves room for the test's own
+//    roundings.
+// The bound is therefore |tail| 2^-49 + |y| 2^-70.  Where c_j = 1 and e' = 0,
+// y = log1p t is small (|t| up to 1/16, |y| down to 2^-4.05) and the tail
+// term dominates; elsewhere |y| >= 0.03 and the test is close to 2^-70 |y|.
+constexpr double LOG64_TAIL_EPS = 0x1p-49;
+constexpr double LOG64_EPS = 0x1p-70;
 
 __device__ __forceinline__ double log64_fast(double x, const Log64Tab& tb, bool& ok) {
   Log64Setup S = log64_setup(x);
@@ -238,7 +253,7 @@ __device__ __forceinline__ double log64_fast(double x, const Log64Tab& tb, bool&
   double ed = (double)S.e2;
   dd el = dd_mul_d(dd{LN2_TD[0].x, LN2_TD[0].y}, ed);
   dd y = dd_add_nc(dd_add_ord(el, dd{L.x, L.y}), l1);
-  double e = fabs(y.hi) * LOG64_EPS;
+  double e = fma(fabs(tail), LOG64_TAIL_EPS, fabs(y.hi) * LOG64_EPS);
   double a = y.hi + (y.lo - e);
   double b = y.hi + (y.lo + e);
   ok = a == b;
