@@ -80,7 +80,8 @@ enum cr_status {
   CR_E_HIP = -6,     /* a HIP runtime call failed; see cr_last_hip_error() */
   CR_E_NOMEM = -7,   /* device allocation of library state failed */
   CR_E_SIZE = -9,    /* n too large */
-  CR_E_TUNE = -10    /* invalid launch configuration, or unreadable/malformed tuning file */
+  CR_E_TUNE = -10,   /* invalid launch configuration, or unreadable/malformed tuning file */
+  CR_E_SCRATCH = -11 /* batch larger than the static scratch of cr_eval_batch_noalloc */
 };
 
 /* out[i] = RN(f(in[i])) for i < n, func = func_id, default implementation.
@@ -140,6 +141,25 @@ int cr_batch_plan_destroy(cr_batch_plan *plan);
  * synchronises the stream once, after copying the tables from host memory
  * and before the launch. */
 int cr_eval_batch(const cr_request *reqs, int32_t num, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as cr_eval_batch, with the same request conventions, results
+ * and errors, but the request and tile tables go into a fixed scratch array
+ * in the library's static device memory instead of stream-ordered
+ * allocations.  The call makes no hipMalloc/hipFree or other allocating
+ * device call.  The scratch holds at most CR_NOALLOC_MAX_REQUESTS requests and
+ * CR_NOALLOC_MAX_TILES tiles, where a request of n elements takes
+ * ceil(n / 2048) tiles (about 10^9 elements in all); larger batches return
+ * CR_E_SCRATCH before anything is copied or launched.  Each device holds one
+ * scratch (about 8.4 MiB, kept until the process ends) shared by every call
+ * on that device: calls on one stream are ordered, but calls that overlap in
+ * time on different streams of one device race on the tables and must not
+ * be made.  Copies the tables from host memory and synchronises the stream
+ * once before launching, as cr_eval_batch does. */
+#define CR_NOALLOC_MAX_REQUESTS 8192
+#define CR_NOALLOC_MAX_TILES (1 << 19)
+int cr_eval_batch_noalloc(const cr_request *reqs, int32_t num, void *stream);
 
 /* Per-device counters of the current device, cumulative since the last reset
  * (paper, Sec. III-B: the cost of lanes sent to the accurate path).

@@ -22,10 +22,14 @@ FLAG_FORCE_FALLBACK = 1
 
 CR_OK = 0
 STATUS = {0: "CR_OK", -1: "CR_E_FUNC", -2: "CR_E_NULL", -3: "CR_E_OVERLAP", -4: "CR_E_ALIGN",
-          -5: "CR_E_IMPL", -6: "CR_E_HIP", -7: "CR_E_NOMEM", -9: "CR_E_SIZE", -10: "CR_E_TUNE"}
+          -5: "CR_E_IMPL", -6: "CR_E_HIP", -7: "CR_E_NOMEM", -9: "CR_E_SIZE", -10: "CR_E_TUNE",
+          -11: "CR_E_SCRATCH"}
+NOALLOC_MAX_REQUESTS = 8192
+NOALLOC_MAX_TILES = 1 << 19
 
 EXPORTED = ["cr_eval", "cr_eval_ex", "cr_available", "cr_batch_plan_create",
-            "cr_batch_plan_launch", "cr_batch_plan_destroy", "cr_eval_batch", "cr_stats_reset",
+            "cr_batch_plan_launch", "cr_batch_plan_destroy", "cr_eval_batch", "cr_eval_batch_noalloc",
+            "cr_stats_reset",
             "cr_stats_read", "cr_status_str", "cr_last_hip_error", "cr_tune_num_variants",
             "cr_tune_variant_info", "cr_tune_get", "cr_tune_set", "cr_tune_reset", "cr_tune_load",
             "cr_tune_save", "cr_autotune"]
@@ -77,6 +81,7 @@ def lib():
         L.cr_batch_plan_launch.argtypes = [vp, vp]
         L.cr_batch_plan_destroy.argtypes = [vp]
         L.cr_eval_batch.argtypes = [ctypes.POINTER(Request), ctypes.c_int32, vp]
+        L.cr_eval_batch_noalloc.argtypes = [ctypes.POINTER(Request), ctypes.c_int32, vp]
         L.cr_stats_reset.argtypes = [vp]
         L.cr_stats_read.argtypes = [vp, ctypes.POINTER(Stats)]
         L.cr_status_str.argtypes = [ctypes.c_int]
@@ -175,6 +180,14 @@ def eval_batch(reqs, stream=None):
     rc = lib().cr_eval_batch(arr, len(reqs), _stream_ptr(stream))
     if rc != CR_OK:
         raise CrError(rc, "cr_eval_batch")
+
+
+def eval_batch_noalloc(reqs, stream=None):
+    """cr_eval_batch_noalloc: the batch with its tables in static scratch."""
+    arr = _requests(reqs)
+    rc = lib().cr_eval_batch_noalloc(arr, len(reqs), _stream_ptr(stream))
+    if rc != CR_OK:
+        raise CrError(rc, "cr_eval_batch_noalloc")
 
 
 def stats_reset(stream=None):

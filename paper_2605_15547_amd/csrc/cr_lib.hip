@@ -782,6 +782,20 @@ struct BTile {
   long long start;
 };
 
+// Static device memory of the library.  Each device the library runs on holds
+// its own copy, zero-initialised when the code object loads, until the
+// process ends.  Host code never passes these names to a kernel or a copy
+// (in host code they are host-side stand-ins): get_state() resolves their
+// per-device addresses with hipGetSymbolAddress.
+//   g_dev_stats  the statistics counters and escape list of every entry point
+//   scratch      the request and tile tables of cr_eval_batch_noalloc:
+//                CR_NOALLOC_MAX_REQUESTS BReq, then CR_NOALLOC_MAX_TILES BTile
+__device__ __align__(256) DevStats g_dev_stats;
+constexpr size_t NOALLOC_REQ_BYTES =
+    ((size_t)CR_NOALLOC_MAX_REQUESTS * sizeof(BReq) + 255) / 256 * 256;
+constexpr size_t SCRATCH_BYTES = NOALLOC_REQ_BYTES + (size_t)CR_NOALLOC_MAX_TILES * sizeof(BTile);
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
 struct BDeferred {
   unsigned n, lanes, waves;
   unsigned req[QCAP];
@@ -977,7 +991,6 @@ __global__ void k_zero_stats(DevStats* st) {
 // ------------------------------------------------------------- host side
 constexpr int MAX_DEV = 64;
 std::mutex g_mu;
-DevStats* g_stats[MAX_DEV];
 std::atomic<unsigned long long> g_elems[MAX_DEV];
 thread_local int t_last_hip = 0;
 
@@ -986,26 +999,42 @@ int hip_fail(hipError_t e) {
   return CR_E_HIP;
 }
 
-int get_stats(DevStats** out) {
+// Per-device addresses of the library's static device memory (g_dev_stats,
+// scratch), resolved once per device with that device current.
+struct DevState {
+  DevStats* stats;
+  unsigned char* scratch;
+};
+DevState g_state[MAX_DEV];
+bool g_state_ok[MAX_DEV];
+
+int get_state(DevState** out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e);
   if (dev < 0 || dev >= MAX_DEV) return CR_E_HIP;
   std::lock_guard<std::mutex> lk(g_mu);
-  if (!g_stats[dev]) {
-    DevStats* p = nullptr;
-    e = hipMalloc(&p, sizeof(DevStats));
-    if (e != hipSuccess) {
-      t_last_hip = (int)e;
-      return CR_E_NOMEM;
-    }
-    e = hipMemset(p, 0, sizeof(DevStats));
+  if (!g_state_ok[dev]) {
+    void* ps = nullptr;
+    void* pb = nullptr;
+    e = hipGetSymbolAddress(&ps, HIP_SYMBOL(g_dev_stats));
     if (e != hipSuccess) return hip_fail(e);
-    e = hipDeviceSynchronize();
+    e = hipGetSymbolAddress(&pb, HIP_SYMBOL(scratch));
     if (e != hipSuccess) return hip_fail(e);
-    g_stats[dev] = p;
+    if (!ps || !pb) return CR_E_HIP;
+    g_state[dev].stats = static_cast<DevStats*>(ps);
+    g_state[dev].scratch = static_cast<unsigned char*>(pb);
+    g_state_ok[dev] = true;
   }
-  *out = g_stats[dev];
+  *out = &g_state[dev];
+  return CR_OK;
+}
+
+int get_stats(DevStats** out) {
+  DevState* ds = nullptr;
+  int rc = get_state(&ds);
+  if (rc) return rc;
+  *out = ds->stats;
   return CR_OK;
 }
 
@@ -1833,6 +1862,40 @@ int cr_eval_batch(const cr_request* reqs, int32_t num, void* stream) {
   return CR_OK;
 }
 
+int cr_eval_batch_noalloc(const cr_request* reqs, int32_t num, void* stream) {
+  if (num > CR_NOALLOC_MAX_REQUESTS) return CR_E_SCRATCH;
+  std::vector<BReq> hr;
+  std::vector<BTile> ht;
+  long long elems = 0;
+  int rc = build_tables(reqs, num, hr, ht, elems);
+  if (rc) return rc;
+  if (ht.empty()) return CR_OK;
+  if (hr.size() > (size_t)CR_NOALLOC_MAX_REQUESTS || ht.size() > (size_t)CR_NOALLOC_MAX_TILES)
+    return CR_E_SCRATCH;
+  DevState* ds = nullptr;
+  rc = get_state(&ds);
+  if (rc) return rc;
+  BReq* dr = reinterpret_cast<BReq*>(ds->scratch);
+  BTile* dt = reinterpret_cast<BTile*>(ds->scratch + NOALLOC_REQ_BYTES);
+  hipStream_t s = (hipStream_t)stream;
+  // stream-ordered after earlier work on s (including an earlier call's
+  // kernels still reading the tables); the host vectors are freed on return,
+  // so wait until the copies have read them
+  hipError_t e = hipMemcpyAsync(dr, hr.data(), hr.size() * sizeof(BReq), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dt, ht.data(), ht.size() * sizeof(BTile), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) {
+    for (const BRange& g : key_ranges(hr, ht)) (void)launch_tiles(dr, dt, g, ds->stats, 0u, s);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  g_elems[dev] += elems;
+  return CR_OK;
+}
+
 int cr_stats_reset(void* stream) {
   DevStats* st = nullptr;
   int rc = get_stats(&st);
@@ -1885,6 +1948,7 @@ const char* cr_status_str(int status) {
     case CR_E_NOMEM: return "device allocation failed";
     case CR_E_SIZE: return "size too large";
     case CR_E_TUNE: return "invalid launch configuration or tuning file";
+    case CR_E_SCRATCH: return "batch exceeds the static scratch of cr_eval_batch_noalloc";
   }
   return "unknown status";
 }
