@@ -5,8 +5,9 @@ Everything is computed here with mpmath at high precision and rounded to
 binary64 (or to double-double pairs hi + lo).  Polynomial coefficients come
 from a weighted minimax fit (Lawson's iteratively reweighted least squares);
 each approximation's error bound is measured on a dense grid with the ROUNDED
-coefficients and inflated by 25%, and is written next to the coefficients so
-the kernels' rounding tests can budget for it.
+coefficients to choose the degree; the bound written next to the coefficients
+(for the kernels' rounding tests to budget for) is a proven one: Taylor's
+theorem with the Lagrange remainder on subintervals (gen/bounds.py).
 
 The paper prints no coefficients (its listings elide them); these are this
 project's own.  Run:  python paper_2605_15547_amd/gen/gen_consts.py
@@ -15,6 +16,9 @@ import os
 import sys
 
 import mpmath as mp
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+import bounds as B  # noqa: E402
 
 mp.mp.prec = 200
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -193,8 +197,8 @@ def gen_exp():
                       -rho, rho)
         if err < mp.mpf(2) ** -63:
             break
-    bound = err * mp.mpf("1.25")
-    emit("// e^r - 1 = r + r^2 (P0 + P1 r + ...), |r| <= %s; |error| <= 2^%.2f (absolute)"
+    bound = B.sup_bound(B.expm1_minus_r([mp.mpf(v) for v in cd], rho))
+    emit("// e^r - 1 = r + r^2 (P0 + P1 r + ...), |r| <= %s; |error| <= 2^%.2f (absolute, proven)"
          % (mp.nstr(rho, 6), log2_of(bound)))
     emit_arr("EXPM1_P", cd, "minimax coefficients P0.. (degree %d)" % (len(cd) - 1))
     emit("#define EXPM1_P_DEG %d" % (len(cd) - 1))
@@ -265,8 +269,10 @@ def gen_log():
             err = max_err(lambda t: g(t) - sum(mp.mpf(cd[k]) * t ** k for k in range(len(cd))), a, b)
             if err < mp.mpf(2) ** -57:
                 break
-        bound = err * mp.mpf("1.25")
-        emit("// log_b(1+t) = K t + t Q(t), K = %s, t in [%s, %s]; |Q error| <= 2^%.2f"
+        bound = B.sup_bound(B.log_b_quotient([mp.mpf(v) for v in cd],
+                                             {"E": "e", "2": "2", "10": "10"}[name],
+                                             mp.mpf(d(K)), a, b))
+        emit("// log_b(1+t) = K t + t Q(t), K = %s, t in [%s, %s]; |Q error| <= 2^%.2f (proven)"
              % (mp.nstr(K, 5), mp.nstr(a, 6), mp.nstr(b, 6), log2_of(bound)))
         emit_arr("LOG%s_Q" % name, cd, "Q coefficients (degree %d)" % (len(cd) - 1))
         emit("#define LOG%s_Q_DEG %d" % (name, len(cd) - 1))
@@ -327,8 +333,9 @@ def gen_trig():
                               mp.mpf(0), rho)
             if err < mp.mpf(2) ** -66:
                 break
-        bound = err * mp.mpf("1.25")
-        emit("// %s: |r| <= pi/64; |approximation error| <= 2^%.2f (absolute)"
+        mk = B.sin_minus_r if name == "SIN_S" else B.cos_minus_1
+        bound = B.sup_bound(mk([mp.mpf(v) for v in cd], rho))
+        emit("// %s: |r| <= pi/64; |approximation error| <= 2^%.2f (absolute, proven)"
              % ("sin r = r + r^3 S(r^2)" if name == "SIN_S" else "cos r - 1 = r^2 C(r^2)",
                 log2_of(bound)))
         emit_arr(name, cd, "coefficients (degree %d in r^2)" % (len(cd) - 1))
@@ -373,8 +380,8 @@ def gen_atan():
                       mp.mpf(0), rho)
         if err < mp.mpf(2) ** -66:
             break
-    emit("// atan t = t + t^3 P(t^2), |t| <= 1/31; |error| <= 2^%.2f (absolute)"
-         % log2_of(err * mp.mpf("1.25")))
+    emit("// atan t = t + t^3 P(t^2), |t| <= 1/31; |error| <= 2^%.2f (absolute, proven)"
+         % log2_of(B.sup_bound(B.atan_minus_t([mp.mpf(v) for v in cd], rho))))
     emit_arr("ATAN_P", cd, "coefficients (degree %d in t^2)" % (len(cd) - 1))
     emit("#define ATAN_P_DEG %d" % (len(cd) - 1))
     N = 12
@@ -427,8 +434,8 @@ def gen_f64():
                                                               for k in range(len(cd))), -rho, rho)
         if err < mp.mpf(2) ** -80:
             break
-    emit("// e^r - 1 = r + r^2 P(r), |r| <= ln2/512; |error| <= 2^%.2f (absolute)"
-         % log2_of(err * mp.mpf("1.25")))
+    emit("// e^r - 1 = r + r^2 P(r), |r| <= ln2/512; |error| <= 2^%.2f (absolute, proven)"
+         % log2_of(B.sup_bound(B.expm1_minus_r([mp.mpf(v) for v in cd], rho))))
     emit_arr("EXP64_P", cd, "coefficients (degree %d)" % (len(cd) - 1))
     emit("#define EXP64_P_DEG %d" % (len(cd) - 1))
     # fast log: log1p(t) = t - t^2/2 + t^3/3 + t^4 S(t), t in [-1/32, 1/16]
@@ -443,8 +450,11 @@ def gen_f64():
                       - t ** 4 * sum(mp.mpf(cd[k]) * t ** k for k in range(len(cd))), a, b)
         if err < mp.mpf(2) ** -78:
             break
-    emit("// log1p t = t - t^2/2 + t^3/3 + t^4 S(t), t in [%s, %s]; |error| <= 2^%.2f (absolute)"
-         % (mp.nstr(a, 6), mp.nstr(b, 6), log2_of(err * mp.mpf("1.25"))))
+    Sm = [mp.mpf(v) for v in cd]
+    emit("// log1p t = t - t^2/2 + t^3/3 + t^4 S(t), t in [%s, %s]; |error| <= 2^%.2f (absolute), "
+         "|S - (log1p t - t + t^2/2 - t^3/3)/t^4| <= 2^%.2f (both proven)"
+         % (mp.nstr(a, 6), mp.nstr(b, 6), log2_of(B.sup_bound(B.log64_absolute(Sm, a, b))),
+            log2_of(B.sup_bound(B.log64_quotient(Sm, a, b)))))
     emit_arr("LOG64_S", cd, "coefficients (degree %d)" % (len(cd) - 1))
     emit("#define LOG64_S_DEG %d" % (len(cd) - 1))
     emit("#define ATANH64_N 16")
