@@ -148,7 +148,7 @@ def bench_batch(torch, crmath, inputs, steps, warmup, stream, impl=1):
     total, nbytes = 0, 0
     for f, n, sd in zip(funcs, lens, seeds):
         n = int(n)
-        x = inputs.workload_f32(f, n, seed=int(sd))
+        x = inputs.workload_f32(f, n, seed=int(sd) % (1 << 62))
         xt = torch.from_numpy(x).cuda()
         ot = torch.empty(2 * n if f == "sincosf" else n, dtype=torch.float32, device="cuda")
         bufs.append((xt, ot))
@@ -207,6 +207,95 @@ def measured_traffic(func, n):
     if t.get("source_hash") != kernel_source_hash() or t.get("elems_per_launch") != n:
         return None
     return t["hbm_bytes_per_launch"].get(func)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(funcs, host, gpu_head, seconds):
+    """The oracle as it is, on a bounded sample: consecutive 2^14-element
+    slices of each function's workload, round robin, for about `seconds` on
+    every host thread; then one thread on 2^17 elements per function (2^20
+    in all, about 1.2 million).  The multi-threaded results are compared bit for bit with
+    the GPU's outputs of the timed step."""
+    from oracle import oracle as O
+    O.build()
+    threads = O.default_threads()
+    m, cnt, rounds = 1 << 14, 0, 0
+    limit = min(v.size for v in gpu_head.values())
+    ref = {f: [] for f in funcs}
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds and (rounds + 1) * m <= limit:
+        for f in funcs:
+            ref[f].append(O.evaluate(f, host[f][rounds * m:(rounds + 1) * m], threads))
+            cnt += m
+        rounds += 1
+    dt = time.perf_counter() - t0
+    compared, mismatches, first = 0, 0, None
+    for f in funcs:
+        if not ref[f]:
+            continue
+        r = np.concatenate(ref[f]).view(np.uint32)
+        g = gpu_head[f][:r.size].view(np.uint32)
+        bad = np.nonzero(r != g)[0]
+        compared += r.size
+        mismatches += int(bad.size)
+        if bad.size and first is None:
+            first = {"func": f, "index": int(bad[0]), "x": hex(int(host[f].view(np.uint32)[bad[0]])),
+                     "gpu": hex(int(g[bad[0]])), "oracle": hex(int(r[bad[0]]))}
+    m1 = 1 << 17
+    t1 = time.perf_counter()
+    for f in funcs:
+        O.evaluate(f, host[f][:m1], 1)
+    dt1 = time.perf_counter() - t1
+    cpu = {"value": round(cnt / dt / 1e9, 6), "unit": "Gelem/s", "cores": threads,
+           "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "per_core_melem_s": round(cnt / dt / 1e6 / threads, 4),
+           "one_thread": {"melem_s": round(m1 * len(funcs) / dt1 / 1e6, 4),
+                          "elements": m1 * len(funcs), "seconds": round(dt1, 2)},
+           "sample": "first %d inputs of each of the %d functions' workloads (%d elements, "
+                     "%.1f s on %d threads); one thread: first 2^17 of each (%.1f s); Ziv "
+                     "loop over fixed-point ball arithmetic"
+                     % (rounds * m, len(funcs), cnt, dt, threads, dt1)}
+    parity = {"against": "oracle", "compared": compared, "mismatches": mismatches,
+              "first_mismatch": first,
+              "what": "the cpu_baseline sample's oracle results vs the GPU outputs of the last "
+                      "timed step, bit for bit"}
+    return cpu, parity
+
+
+def split_vs_f64(per, extra, n):
+    """Throughput of the binary32-only implementation over the binary64-internal
+    one, per family (harmonic: total elements over total time)."""
+    out = {}
+    pairs = [("exp_log_family", {"per_func": per}, extra.get("exp_log_family_split_f32")),
+             ("trig_hyperbolic_family", extra.get("trig_hyperbolic_family"),
+              extra.get("trig_hyperbolic_family_split_f32"))]
+    for name, f64, spl in pairs:
+        if not f64 or not spl:
+            continue
+        both = [f for f in f64["per_func"] if f64["per_func"].get(f) and spl["per_func"].get(f)]
+        if not both:
+            continue
+        t_s = sum(spl["per_func"][f]["ms"] for f in both)
+        t_d = sum(f64["per_func"][f]["ms"] for f in both)
+        out[name] = {"functions": both,
+                     "split_gelem_s": round(len(both) * n / (t_s * 1e-3) / 1e9, 2),
+                     "f64_gelem_s": round(len(both) * n / (t_d * 1e-3) / 1e9, 2),
+                     "ratio": round(t_d / t_s, 3)}
+    b1, b2 = extra.get("ragged_batch"), extra.get("ragged_batch_split_f32")
+    if b1 and b2:
+        out["ragged_batch"] = {"split_gelem_s": b2["gelem_s"], "f64_gelem_s": b1["gelem_s"],
+                               "ratio": round(b2["gelem_s"] / b1["gelem_s"], 3)}
+    return out or None
 
 
 def main():
@@ -307,6 +396,11 @@ def main():
             "traffic": measured_traffic(dom, n),
             "bytes_per_elem": 8, "elems_per_launch": n}
 
+    # the leading outputs of the last timed step, for the check against the
+    # oracle results the cpu_baseline leg computes
+    check_n = min(n, 1 << 23)
+    gpu_head = {f: outs[f][:check_n].cpu().numpy() for f in funcs}
+
     copy_ms = None
     if a.copy_ref:
         # a plain device-to-device copy of the same size: the reference used to
@@ -342,26 +436,9 @@ def main():
             torch, crmath, inputs, TRIG, n, 2, a.steps, a.warmup,
             stream)
 
-    cpu = None
+    cpu, parity = None, None
     if not a.no_cpu_baseline:
-        # the oracle as it is, on a bounded sample: consecutive 2^14-element
-        # slices of each function's workload, round robin, for about 12 s
-        from oracle import oracle as O
-        O.build()
-        threads = O.default_threads()
-        m, cnt, rounds = 1 << 14, 0, 0
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < a.cpu_seconds:
-            for f in funcs:
-                O.evaluate(f, host[f][rounds * m:(rounds + 1) * m], threads)
-                cnt += m
-            rounds += 1
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(cnt / dt / 1e9, 6), "unit": "Gelem/s", "cores": threads,
-               "kind": "oracle",
-               "sample": "first %d inputs of each of the %d functions' workloads (%d elements, "
-                         "%.1f s); Ziv loop over fixed-point ball arithmetic"
-                         % (rounds * m, len(funcs), cnt, dt)}
+        cpu, parity = cpu_baseline(funcs, host, gpu_head, a.cpu_seconds)
 
     rec = {"metric": "correctly rounded Gelem/s (exp/log family, binary32), bit-exact",
            "value": round(value, 2), "unit": "Gelem/s", "n_gpus": 1, "steps": a.steps,
@@ -377,17 +454,9 @@ def main():
            "fallback": {"lanes": st["fallback_lanes"], "waves": st["fallback_waves"],
                         "escapes": st["escapes"],
                         "lane_rate": st["fallback_lanes"] / max(1, total_elems)},
-           "roofline": roof, "cpu_baseline": cpu, "other_workloads": extra}
-    sp = extra.get("exp_log_family_split_f32")
-    if sp:
-        both = [f for f in funcs if sp["per_func"].get(f)]
-        t_split = sum(sp["per_func"][f]["ms"] for f in both)
-        t_f64 = sum(per[f]["ms"] for f in both)
-        rec["split_f32_vs_f64"] = {
-            "functions": both,
-            "split_gelem_s": round(len(both) * n / (t_split * 1e-3) / 1e9, 2),
-            "f64_gelem_s": round(len(both) * n / (t_f64 * 1e-3) / 1e9, 2),
-            "ratio": round(t_f64 / t_split, 3)}
+           "roofline": roof, "cpu_baseline": cpu, "parity_vs_oracle": parity,
+           "other_workloads": extra}
+    rec["split_f32_vs_f64"] = split_vs_f64(per, extra, n)
     if copy_ms is not None:
         rec["copy_ref"] = {"ms": round(copy_ms, 4), "bytes": 8 * n,
                            "gb_s": round(8 * n / (copy_ms * 1e-3) / 1e9, 1)}
