@@ -728,7 +728,7 @@ enum {
   F_EXPF = 0, F_EXP2F, F_EXP10F, F_EXPM1F, F_LOGF, F_LOG2F, F_LOG10F, F_LOG1PF, F_RSQRTF,
   F_SINF, F_COSF, F_SINCOSF, F_TANF, F_ASINF, F_ACOSF, F_ATANF, F_SINHF, F_COSHF, F_TANHF,
   F_NUM32,
-  F_EXP = 64, F_LOG = 65
+  F_EXP = 64, F_LOG = 65, F_EXP2 = 66
 };
 /* internal kinds (sincosf is evaluated as sin and as cos) */
 enum { K_EXP, K_EXP2, K_EXP10, K_EXPM1, K_LOG, K_LOG2, K_LOG10, K_LOG1P, K_RSQRT,
@@ -1105,13 +1105,19 @@ static int special(int kind, int fmt, double x, uint64_t *r) {
       if (x == 0) { *r = one; return 1; }
       if (isinf(x)) { *r = x > 0 ? inf : 0; return 1; }
       double hiT, loT;
-      if (fmt) { hiT = 710; loT = -746; }
+      /* binary64 exp2: 2^1024 overflows; 2^-1075 is exactly the midpoint
+       * between 0 and the smallest subnormal (ties to even give +0) and
+       * anything below rounds to 0 */
+      if (fmt && kind == K_EXP2) { hiT = 1024; loT = -1075; }
+      else if (fmt) { hiT = 710; loT = -746; }
       else if (kind == K_EXP) { hiT = 100; loT = -110; }
       else if (kind == K_EXP2) { hiT = 128; loT = -151; }
       else { hiT = 40; loT = -47; }
       if (x >= hiT) { *r = inf; return 1; }
       if (x <= loT) { *r = 0; return 1; }
-      if (kind == K_EXP2 && x == -150) { *r = 0; return 1; } /* exact midpoint, ties to even */
+      /* binary32: 2^-150 is exactly the midpoint between 0 and 2^-149 (ties
+       * to even give +0); in binary64 it is an ordinary representable value */
+      if (!fmt && kind == K_EXP2 && x == -150) { *r = 0; return 1; }
       return 0;
     }
     case K_EXPM1:
@@ -1212,6 +1218,7 @@ static int kind_of(int f) {
   if (f >= 0 && f < F_NUM32) return map[f];
   if (f == F_EXP) return K_EXP;
   if (f == F_LOG) return K_LOG;
+  if (f == F_EXP2) return K_EXP2;
   return -2;
 }
 
@@ -1534,7 +1541,7 @@ int64_t cr_oracle_scan_f32(int func_id, uint32_t lo, uint64_t hi, double h_prefi
   return shared;
 }
 
-/* Sampled hard-case scan for binary64 exp/log: a quad-precision estimate
+/* Sampled hard-case scan for binary64 exp/log/exp2: a quad-precision estimate
  * (libquadmath) preselects candidates within 2^-h_prefilter ulp of a
  * binary64 midpoint; the oracle then measures each candidate's hardness. */
 #include <quadmath.h>
@@ -1567,7 +1574,9 @@ static void *scan64_run(void *arg) {
     double x = s->x[i];
     uint64_t enc;
     if (isnan(x) || special(s->kind, 1, x, &enc)) continue;
-    __float128 y = s->kind == K_EXP ? expq((__float128)x) : logq((__float128)x);
+    __float128 y = s->kind == K_EXP    ? expq((__float128)x)
+                   : s->kind == K_EXP2 ? exp2q((__float128)x)
+                                       : logq((__float128)x);
     if (!(mid_dist64q(y) < thr)) continue;
     uint64_t xb, o;
     double h = 0;
@@ -1589,7 +1598,7 @@ static void *scan64_run(void *arg) {
 int64_t cr_oracle_scan_f64(int func_id, const double *x, size_t n, double h_prefilter,
                            double h_keep, double *out_x, double *out_h, int64_t max_out,
                            int nthreads) {
-  if (func_id != F_EXP && func_id != F_LOG) return -1;
+  if (func_id != F_EXP && func_id != F_LOG && func_id != F_EXP2) return -1;
   if (nthreads < 1) nthreads = 1;
   if (nthreads > 256) nthreads = 256;
   pthread_mutex_t mu = PTHREAD_MUTEX_INITIALIZER;

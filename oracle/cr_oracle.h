@@ -8,7 +8,7 @@
  *
  * What it computes (paper, Sec. I and Sec. II-A): for an input encoding x
  * and a function f, the correctly rounded value RN_even(f(x)) in binary32
- * (single precision functions) or binary64 (exp, log), where f(x) is the
+ * (single precision functions) or binary64 (exp, log, exp2), where f(x) is the
  * exact real value.  The evaluation is a Ziv loop (Sec. I): f(x) is
  * enclosed in an interval with a from-scratch fixed-point multiprecision
  * ball arithmetic; when both ends of the interval round to the same
@@ -20,10 +20,10 @@
  *   0 expf   1 exp2f   2 exp10f  3 expm1f  4 logf   5 log2f  6 log10f
  *   7 log1pf 8 rsqrtf  9 sinf   10 cosf   11 sincosf 12 tanf 13 asinf
  *  14 acosf 15 atanf  16 sinhf  17 coshf  18 tanhf  64 exp (binary64)
- *  65 log (binary64)
+ *  65 log (binary64)  66 exp2 (binary64; the paper's binary64 exp2, Sec. II-B)
  *
  * Conventions: in/out are HOST pointers.  Element type follows the id
- * (float for 0..18, double for 64, 65).  sincosf writes 2n floats, planar:
+ * (float for 0..18, double for 64, 65, 66).  sincosf writes 2n floats, planar:
  * out[0..n) = sin, out[n..2n) = cos.
  * Return value: 0 on success, negative on a bad id / null pointer, or -9 if
  * some element did not resolve within the precision cap (its output is then
@@ -57,7 +57,7 @@ int64_t cr_oracle_scan_f32(int func_id, uint32_t lo, uint64_t hi, double h_prefi
                            double h_keep, uint32_t *out_bits, double *out_h,
                            int64_t max_out, int nthreads);
 
-/* Sampled hard-case scan for binary64 exp (64) / log (65) over the n given
+/* Sampled hard-case scan for binary64 exp (64) / log (65) / exp2 (66) over the n given
  * inputs: a quad-precision estimate preselects candidates, the oracle keeps
  * those with hardness >= h_keep.  Same output convention as the f32 scan. */
 int64_t cr_oracle_scan_f64(int func_id, const double *x, size_t n, double h_prefilter,

@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
 CPU-baseline leg of the benchmark.  The GPU library never imports it.
 
 The oracle returns RN_even(f(x)) for binary32 functions (ids 0..18) and
-binary64 exp/log (ids 64, 65), computed by a Ziv loop over a from-scratch
+binary64 exp/log/exp2 (ids 64, 65, 66), computed by a Ziv loop over a from-scratch
 fixed-point ball arithmetic (see cr_oracle.c for the method and citations).
 """
 import ctypes
@@ -22,6 +22,7 @@ FUNCS32 = ["expf", "exp2f", "exp10f", "expm1f", "logf", "log2f", "log10f", "log1
 FUNC_ID = {name: i for i, name in enumerate(FUNCS32)}
 FUNC_ID["exp"] = 64
 FUNC_ID["log"] = 65
+FUNC_ID["exp2"] = 66
 
 
 def build(force=False):

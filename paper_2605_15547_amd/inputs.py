@@ -16,8 +16,9 @@ its GPU tables, so these are synthetic stand-ins of the shapes it names):
   * trig/hyperbolic family: random sign and exponent field uniform in
     [97, 254] (|x| in 2^-30 .. 2^127) for sin/cos/sincos/tan/atan; uniform
     in the domain for the others.
-  * binary64 exp/log: exp uniform in [-745, 709.7]; log = ldexp(1+f, E) with
-    E uniform in [-1074, 1023]; 1e-4 of the elements from the hard set.
+  * binary64 exp/log/exp2: exp uniform in [-745, 709.7]; log = ldexp(1+f, E)
+    with E uniform in [-1074, 1023]; exp2 uniform in [-20, 20]; 1e-4 of the
+    elements from the hard set.
   * ragged batch: 4096 requests, function uniform over the 19 binary32
     functions, length floor(2^(20 u)) capped at 2^20.
 """
@@ -35,6 +36,8 @@ FUNCS32 = ["expf", "exp2f", "exp10f", "expm1f", "logf", "log2f", "log10f", "log1
 FUNC_ID = {name: i for i, name in enumerate(FUNCS32)}
 FUNC_ID["exp"] = 64
 FUNC_ID["log"] = 65
+FUNC_ID["exp2"] = 66
+F64_FUNCS = ("exp", "log", "exp2")
 EXPLOG_FAMILY = FUNCS32[:9]
 TRIG_FAMILY = FUNCS32[9:]
 
@@ -96,12 +99,12 @@ def encoding_uniform_f32(st, n, lo_bits, hi_bits):
 def hard_set(func):
     """The function's hard-to-round inputs found by the oracle's exhaustive scan
     (tests/golden/hard/<func>.u32, written by tests/golden/make_hard_sets.py)."""
-    path = os.path.join(GOLDEN, "hard", func + (".u64" if func in ("exp", "log") else ".u32"))
+    path = os.path.join(GOLDEN, "hard", func + (".u64" if func in F64_FUNCS else ".u32"))
     if not os.path.exists(path):
         return None
-    dt = np.uint64 if func in ("exp", "log") else np.uint32
+    dt = np.uint64 if func in F64_FUNCS else np.uint32
     a = np.fromfile(path, dtype=dt)
-    return a.view(np.float64 if func in ("exp", "log") else np.float32)
+    return a.view(np.float64 if func in F64_FUNCS else np.float32)
 
 
 def edge_inputs_expf():
@@ -179,10 +182,14 @@ def expf_correctness_set(n_uniform=1 << 20):
 
 
 def workload_f64(func, n, seed=None):
-    """binary64 exp/log workload with 1e-4 of the elements from the hard set."""
+    """binary64 exp/log/exp2 workload with 1e-4 of the elements from the hard
+    set.  exp2: uniform in [-20, 20], the range of the paper's binary64 exp2
+    measurements (Sec. III, Table IV)."""
     st = Stream(4000 + FUNC_ID[func] if seed is None else seed)
     if func == "exp":
         x = -745.0 + (709.7 + 745.0) * st.uniform(n)
+    elif func == "exp2":
+        x = -20.0 + 40.0 * st.uniform(n)
     elif func == "log":
         E = -1074 + st.below(n, 1023 + 1074 + 1)
         f = (st.u64(n) >> np.uint64(12)).astype(np.float64) * 2.0 ** -52

@@ -8,12 +8,14 @@ library.
 
 binary32 functions: exhaustive scan of all 2^32 encodings; the 2048 inputs
 with the largest h are kept (tests/golden/hard/<func>.u32, little endian).
-binary64 exp/log: a quad-precision-prefiltered scan of 2^26 seeded samples of
-the binary64 workload plus two constructed families near the points where the
+binary64 exp/log/exp2: a quad-precision-prefiltered scan of 2^26 seeded
+samples of the binary64 workload (exp2: half on [-20, 20], half over the whole
+range) plus, for exp and log, two constructed families near the points where the
 Taylor expansion puts f(x) next to a midpoint (exp near 0, log near 1); 1024
 of each kind are kept (tests/golden/hard/<func>.u64).
 
 Usage: python tests/golden/make_hard_sets.py [--threads N] [--only f1,f2]
+(all binary32 functions and binary64 exp, log by default; exp2 with --only exp2)
 """
 import argparse
 import hashlib
@@ -67,6 +69,11 @@ def scan64(func, threads):
     st = I.Stream(7000 + I.FUNC_ID[func])
     if func == "exp":
         x = -745.0 + (709.7 + 745.0) * st.uniform(n)
+    elif func == "exp2":
+        # half on [-20, 20] (where the paper measures binary64 exp2), half over
+        # the whole range with a finite nonzero result
+        x = np.concatenate([-20.0 + 40.0 * st.uniform(n // 2),
+                            -1075.0 + (1024.0 + 1075.0) * st.uniform(n - n // 2)])
     else:
         E = -1074 + st.below(n, 1023 + 1074 + 1)
         f = (st.u64(n) >> np.uint64(12)).astype(np.float64) * 2.0 ** -52
@@ -74,17 +81,21 @@ def scan64(func, threads):
     rx, rh, cnt = O.scan_f64(func, x, 15.0, 16.0, max_out=1 << 20, nthreads=threads)
     o = np.lexsort((rx, -rh))[:K64]
     rx, rh = rx[o], rh[o]
-    cx = constructed64(func)
-    ch = O.hardness(func, cx, threads)
-    o = np.lexsort((cx, -ch))[:K64]
-    cx, ch = cx[o], ch[o]
+    if func == "exp2":  # no constructed family: the sampled scan only
+        cx = ch = np.zeros(0)
+    else:
+        cx = constructed64(func)
+        ch = O.hardness(func, cx, threads)
+        o = np.lexsort((cx, -ch))[:K64]
+        cx, ch = cx[o], ch[o]
     allx = np.concatenate([rx, cx])
     path = os.path.join(OUT, func + ".u64")
     allx.view(np.uint64).astype("<u8").tofile(path)
     return {"sampled": n, "sample_count_h_ge_16": int(cnt), "kept_sampled": int(rx.size),
             "sampled_max_h": float(rh.max()), "sampled_min_h_kept": float(rh.min()),
-            "kept_constructed": int(cx.size), "constructed_max_h": float(ch.max()),
-            "constructed_min_h_kept": float(ch.min()),
+            "kept_constructed": int(cx.size),
+            "constructed_max_h": float(ch.max()) if ch.size else None,
+            "constructed_min_h_kept": float(ch.min()) if ch.size else None,
             "seconds": round(time.time() - t, 1), "sha256": sha(path)}
 
 
@@ -99,7 +110,7 @@ def main():
     idx = json.load(open(idx_path)) if os.path.exists(idx_path) else {}
     funcs = a.only.split(",") if a.only else I.FUNCS32 + ["exp", "log"]
     for func in funcs:
-        r = scan64(func, a.threads) if func in ("exp", "log") else scan32(func, a.threads)
+        r = scan64(func, a.threads) if func in ("exp", "log", "exp2") else scan32(func, a.threads)
         idx[func] = r
         print(func, r, flush=True)
         idx["_command"] = "python tests/golden/make_hard_sets.py"

@@ -35,7 +35,8 @@ MPF = {"expf": mp.exp, "exp2f": lambda x: mp.power(2, x), "exp10f": lambda x: mp
        "log10f": mp.log10, "log1pf": mp.log1p, "rsqrtf": lambda x: 1 / mp.sqrt(x),
        "sinf": mp.sin, "cosf": mp.cos, "tanf": mp.tan, "asinf": mp.asin, "acosf": mp.acos,
        "atanf": mp.atan, "sinhf": mp.sinh, "coshf": mp.cosh, "tanhf": mp.tanh,
-       "exp": mp.exp, "log": mp.log}
+       "exp": mp.exp, "log": mp.log, "exp2": lambda x: mp.power(2, x)}
+F64 = ("exp", "log", "exp2")
 
 
 def mp_round(v, P, emin, emax):
@@ -66,7 +67,7 @@ def mp_round(v, P, emin, emax):
 def mp_ref(func, x):
     mp.mp.prec = 400
     v = MPF[func](mp.mpf(float(x)))
-    if func in ("exp", "log"):
+    if func in F64:
         return mp_round(v, 53, -1022, 1023)
     return np.float32(mp_round(v, 24, -126, 127))
 
@@ -98,29 +99,34 @@ def sample(func, n, seed):
         return rng.random(n) * (712 + 750) - 750
     if func == "log":
         return np.ldexp(1 + rng.random(n), rng.integers(-1074, 1024, n))
+    if func == "exp2":
+        # half over the whole range (overflow and the subnormal results included),
+        # half on [-20, 20], where the paper measures binary64 exp2
+        return np.concatenate([rng.random(n - n // 2) * (1030 + 1080) - 1080,
+                               rng.random(n // 2) * 40 - 20])
     return (rng.random(n) * 220 - 110).astype(np.float32)
 
 
-@pytest.mark.parametrize("func", F32 + ["exp", "log"])
+@pytest.mark.parametrize("func", F32 + list(F64))
 def test_brute_force_vs_mpmath(oracle, func):
     """Random inputs across the whole domain: oracle == mpmath (400 bits)."""
     x = sample(func, 160, 11 + (zlib.crc32(func.encode()) % 1000))
     got = oracle.evaluate(func, x)
     for xi, gi in zip(x, got):
         ref = mp_ref(func, xi)
-        if func in ("exp", "log"):
+        if func in F64:
             assert u64(gi) == u64(ref), (func, float(xi), gi, ref)
         else:
             assert u32(gi) == u32(ref), (func, float(xi), gi, ref)
 
 
-@pytest.mark.parametrize("func", F32 + ["exp", "log"])
+@pytest.mark.parametrize("func", F32 + list(F64))
 def test_hard_set_vs_mpmath(oracle, func):
     """The hardest inputs found by the exhaustive scan: oracle == mpmath."""
-    path = os.path.join(GOLD, "hard", func + (".u64" if func in ("exp", "log") else ".u32"))
+    path = os.path.join(GOLD, "hard", func + (".u64" if func in F64 else ".u32"))
     if not os.path.exists(path):
         pytest.skip("hard set not generated")
-    dt = (np.uint64, np.float64) if func in ("exp", "log") else (np.uint32, np.float32)
+    dt = (np.uint64, np.float64) if func in F64 else (np.uint32, np.float32)
     x = np.fromfile(path, dtype=dt[0]).view(dt[1])[:24]
     got = oracle.evaluate(func, x)
     for xi, gi in zip(x, got):
@@ -155,6 +161,60 @@ def test_exact_powers(oracle):
     k = np.arange(-74, 64)
     assert np.array_equal(u32(oracle.evaluate("rsqrtf", np.ldexp(np.float32(1), 2 * k))),
                           u32(np.ldexp(np.float32(1), -k)))
+
+
+def rn53_root(num, n):
+    """RN to 53 bits of num^(1/n) for an integer num in [1, 2^n), decided with
+    exact integer comparisons (the root is irrational for the num used, so no
+    tie can occur): M in [2^52, 2^53) with M^n <= num 2^(52 n) < (M+1)^n, then
+    up when the midpoint (2M+1)/2 lies below the root."""
+    t = num << (52 * n)
+    lo, hi = 1 << 52, 1 << 53
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if mid ** n <= t:
+            lo = mid
+        else:
+            hi = mid
+    M = lo
+    if (2 * M + 1) ** n < (num << (53 * n)):
+        M += 1
+    return M
+
+
+def test_exact_powers_binary64(oracle):
+    """binary64 exp2 (paper, Sec. II-B): exp2(k) = 2^k for every integer k with
+    a representable result, the one exact midpoint exp2(-1075) = +0 (ties to
+    even) and its neighbours, overflow at 1024, and exp2(k + 1/2),
+    exp2(k + 1/4), exp2(k + 3/4) against 2^k times the correctly rounded
+    roots of 2, 2 and 8, decided in integer arithmetic."""
+    k = np.arange(-1074, 1024)
+    got = u64(oracle.evaluate("exp2", k.astype(np.float64)))
+    assert np.array_equal(got, u64(np.ldexp(1.0, k)))
+    x = np.array([-1075.0, np.nextafter(-1075.0, 0), np.nextafter(-1075.0, -2000), 1024.0,
+                  np.nextafter(1024.0, 0), -1e300, 1e300], dtype=np.float64)
+    r = oracle.evaluate("exp2", x)
+    assert u64(r[:3]).tolist() == [0, 1, 0]
+    assert np.isinf(r[3]) and np.isfinite(r[4]) and r[4] > 1.7e308
+    assert u64(r[5:]).tolist() == [0, 0x7FF0000000000000]
+    for frac, num, n in ((0.5, 2, 2), (0.25, 2, 4), (0.75, 8, 4)):
+        M = rn53_root(num, n)
+        k = np.arange(-1022, 1023)
+        got = oracle.evaluate("exp2", k + frac)
+        assert np.array_equal(u64(got), u64(np.ldexp(float(M) * 2.0 ** -52, k))), frac
+    sp = np.array([0.0, -0.0, np.inf, -np.inf], dtype=np.float64)
+    assert u64(oracle.evaluate("exp2", sp)).tolist() == [u64(1.0)] * 2 + [0x7FF0000000000000, 0]
+    nans = np.array([0x7FF8000000000000, 0xFFF8000000000000, 0x7FF0000000000001],
+                    dtype=np.uint64)
+    assert u64(oracle.evaluate("exp2", nans.view(np.float64))).tolist() == \
+        (nans | np.uint64(0x0008000000000000)).tolist()
+
+
+def test_exp2_binary64_monotone(oracle):
+    rng = np.random.default_rng(17)
+    x = np.sort(np.concatenate([rng.uniform(-1080, 1030, 4000), rng.uniform(-20, 20, 4000)]))
+    y = oracle.evaluate("exp2", x)
+    assert np.all(y[1:] >= y[:-1])
 
 
 def test_exact_scalars(oracle):
