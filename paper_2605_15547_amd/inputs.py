@@ -212,3 +212,27 @@ def batch_requests(num=4096, seed=5000, max_log2=20):
     lens = np.minimum(2 ** max_log2, np.floor(2.0 ** (max_log2 * u))).astype(np.int64)
     seeds = (st.u64(num) >> np.uint64(1)).astype(np.int64)
     return funcs, lens, seeds
+
+
+# ------------------------------------------------------- application workloads
+COMPLEX_FUNCS = ("cexpf", "clogf", "csinf")
+
+
+def complex_workload(n, seed=6000, lo=-40.0, hi=40.0):
+    """n binary32 complex numbers, interleaved (re, im), both parts uniform in
+    [lo, hi] (the paper's range for its complex expf/logf/sinf runs is
+    [-40, 40], Sec. III-A)."""
+    st = Stream(seed)
+    return uniform_f32(st, 2 * n, lo, hi)
+
+
+def dft_workload(n_samples, n_freqs, seed=7000):
+    """Spectral interpolation inputs: n_samples binary32 time samples uniform
+    in [-1, 1], and one binary32 per-sample angle w_k = RN32(2 pi f_k / N)
+    per output frequency, f_k uniform in [0, N/2) in bins (non-integer, so
+    between the bins an FFT would compute)."""
+    st = Stream(seed)
+    x = uniform_f32(st, n_samples, -1.0, 1.0)
+    f = st.uniform(n_freqs) * (n_samples / 2.0)
+    w = (2.0 * np.pi * f / n_samples).astype(np.float32)
+    return x, w
