@@ -15,11 +15,13 @@ the CPU oracle (oracle/) on a bounded sample of the same inputs.
 
 other_workloads (left out with --headline-only) reports, outside the headline
 value: the trig/inverse-trig/hyperbolic family at the same size, binary64
-exp/log on 2^24 inputs each, the paper's GPU metric (correctly rounded over
-the platform's ~1-ulp library functions for expf, logf, sincosf, exp, log),
+exp/log/exp2 on 2^24 inputs each (exp2 uniform in [-20, 20], the paper's
+range), the paper's GPU metric (correctly rounded over the platform's ~1-ulp
+library functions for expf, logf, sincosf, exp, log, exp2),
 the ragged batch of 4096 mixed requests evaluated by one graph launch per step
-(plan creation timed separately), and the binary32-only implementation on the
-same workloads.
+(plan creation timed separately), the binary32-only implementation on the
+same workloads, and the paper's application workloads (complex expf/logf/sinf
+on 2^24 complex numbers, a 2^20-sample brute-force DFT at 256 frequencies).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n LOG2N]
 """
@@ -31,6 +33,9 @@ import time
 
 import numpy as np
 
+# binary64 functions (16 bytes per element)
+F64 = ("exp", "log", "exp2")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -40,7 +45,7 @@ TRIG = ["sinf", "cosf", "sincosf", "tanf", "asinf", "acosf", "atanf", "sinhf", "
 
 
 def bytes_per_elem(func):
-    return 16 if func in ("exp", "log") else (12 if func == "sincosf" else 8)
+    return 16 if func in F64 else (12 if func == "sincosf" else 8)
 
 
 def settle(fn, seconds, torch):
@@ -61,7 +66,7 @@ def bench_family(torch, crmath, inputs, funcs, n, impl, steps, warmup, stream, s
         if not crmath.available(f, impl):
             res[f] = None
             continue
-        x = inputs.workload_f64(f, n) if f in ("exp", "log") else inputs.workload_f32(f, n)
+        x = inputs.workload_f64(f, n) if f in F64 else inputs.workload_f32(f, n)
         xt = torch.from_numpy(x).cuda()
         ot = torch.empty(2 * n if f == "sincosf" else n, dtype=xt.dtype, device="cuda")
         bufs[f] = (xt, ot)
@@ -96,7 +101,7 @@ def bench_family(torch, crmath, inputs, funcs, n, impl, steps, warmup, stream, s
             "per_func": res}
 
 
-PAPER_GPU_FUNCS = ["expf", "logf", "sincosf", "exp", "log"]
+PAPER_GPU_FUNCS = ["expf", "logf", "sincosf", "exp", "log", "exp2"]
 
 
 def bench_vs_ulp(torch, crmath, inputs, n, steps, warmup, stream):
@@ -113,8 +118,8 @@ def bench_vs_ulp(torch, crmath, inputs, n, steps, warmup, stream):
     sp = crmath._stream_ptr(stream)
     out = {}
     for f in PAPER_GPU_FUNCS:
-        m = n >> 2 if f in ("exp", "log") else n
-        x = inputs.workload_f64(f, m) if f in ("exp", "log") else inputs.workload_f32(f, m)
+        m = n >> 2 if f in F64 else n
+        x = inputs.workload_f64(f, m) if f in F64 else inputs.workload_f32(f, m)
         xt = torch.from_numpy(x).cuda()
         ot = torch.empty(2 * m if f == "sincosf" else m, dtype=xt.dtype, device="cuda")
         fid = crmath.FUNC_ID[f]
@@ -138,6 +143,71 @@ def bench_vs_ulp(torch, crmath, inputs, n, steps, warmup, stream):
     torch.cuda.empty_cache()
     log("bench: vs 1-ulp library", out)
     return out
+
+
+def bench_complex(torch, crmath, inputs, n, steps, warmup, stream):
+    """The paper's complex expf/logf/sinf application (Sec. III-A): n complex
+    numbers per function, parts uniform in [-40, 40]; 16 bytes per element."""
+    sp = crmath._stream_ptr(stream)
+    z = inputs.complex_workload(n)
+    zt = torch.from_numpy(z).cuda()
+    ot = torch.empty_like(zt)
+    res = {}
+    for f in crmath.COMPLEX:
+        def run():
+            crmath.eval_ptr(f, zt.data_ptr(), ot.data_ptr(), n, 0, 0, sp)
+        settle(run, 0.2, torch)
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        crmath.stats_reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        st = crmath.stats_read()
+        ms = e0.elapsed_time(e1) / steps
+        gbs = 16 * n / (ms * 1e-3) / 1e9
+        res[f] = {"ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                  "gb_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                  "fallback_lane_rate": st["fallback_lanes"] / (n * steps),
+                  "escapes": st["escapes"]}
+    del zt, ot
+    torch.cuda.empty_cache()
+    log("bench: complex", {k: v["gelem_s"] for k, v in res.items()})
+    return {"elems_per_function": n, "unit": "10^9 complex numbers per second",
+            "bytes_per_elem": 16, "inputs": "re, im uniform in [-40, 40]", "per_func": res}
+
+
+def bench_dft(torch, crmath, inputs, n, m, steps, warmup, stream):
+    """Spectral interpolation by brute-force DFT (Sec. III-A): m outputs of n
+    samples each, one correctly rounded sincosf per (output, sample)."""
+    x, w = inputs.dft_workload(n, m)
+    xt, wt = torch.from_numpy(x).cuda(), torch.from_numpy(w).cuda()
+    out = torch.empty((m, 2), dtype=torch.float64, device="cuda")
+    sp = crmath._stream_ptr(stream)
+
+    def run():
+        crmath.dft_ptr(xt.data_ptr(), n, wt.data_ptr(), m, out.data_ptr(), 0, sp)
+    settle(run, 0.3, torch)
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    r = {"samples": n, "outputs": m, "ms": round(ms, 4),
+         "gsincos_s": round(n * m / (ms * 1e-3) / 1e9, 2),
+         "what": "terms x[j] (cos t - i sin t), t = RN32(w_k j), per second; sincosf "
+                 "correctly rounded, double-double sums"}
+    log("bench: dft", r)
+    return r
 
 
 def bench_batch(torch, crmath, inputs, steps, warmup, stream, impl=1):
@@ -423,9 +493,13 @@ def main():
         extra["trig_hyperbolic_family"] = bench_family(
             torch, crmath, inputs, TRIG, n, a.impl, a.steps, a.warmup, stream)
         extra["binary64_exp_log"] = bench_family(
-            torch, crmath, inputs, ["exp", "log"], 1 << 24, 0, a.steps, a.warmup, stream)
+            torch, crmath, inputs, list(F64), 1 << 24, 0, a.steps, a.warmup, stream)
         extra["vs_ulp_library"] = bench_vs_ulp(torch, crmath, inputs, n, a.steps, a.warmup,
                                                stream)
+        extra["complex_functions"] = bench_complex(torch, crmath, inputs, 1 << 24, a.steps,
+                                                   a.warmup, stream)
+        extra["spectral_interpolation_dft"] = bench_dft(torch, crmath, inputs, 1 << 20, 256,
+                                                        a.steps, a.warmup, stream)
         extra["ragged_batch"] = bench_batch(torch, crmath, inputs, a.steps, a.warmup, stream)
         extra["ragged_batch_split_f32"] = bench_batch(torch, crmath, inputs, a.steps, a.warmup,
                                                       stream, impl=2)

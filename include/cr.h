@@ -5,18 +5,18 @@
  * (ties to even), element by element, on the GPU: the 19 single precision
  * functions the paper lists (Sec. II-A: acosf, asinf, atanf, cosf, coshf,
  * expf, exp2f, exp10f, expm1f, log10f, log1pf, log2f, logf, sincosf, sinf,
- * sinhf, rsqrtf, tanf, tanhf) and double precision exp and log (the paper
- * studies double precision exp2 and log in Sec. II-B; this library provides
- * exp and log).  "Correctly rounded" means the result is RN(f(x)) for the
- * exact real f(x) (paper, Sec. I).  Only round-to-nearest-even is provided,
+ * sinhf, rsqrtf, tanf, tanhf) and double precision exp2 and log (the
+ * functions the paper studies in Sec. II-B; exp2 with the paper's three
+ * 16-entry tables) plus double precision exp.  "Correctly rounded" means the
+ * result is RN(f(x)) for the exact real f(x) (paper, Sec. I).  Only round-to-nearest-even is provided,
  * as in the paper's GPU experiments (Sec. III-C).
  *
  * Conventions shared by every entry point:
  *  - in/out are DEVICE pointers owned by the caller, on the current HIP
  *    device; the stream argument is a hipStream_t (NULL = default stream).
- *  - element type follows func_id: float for ids 0..18, double for 64, 65;
- *    n counts input elements.  sincosf writes 2n floats, planar:
- *    out[0..n) = sin(in), out[n..2n) = cos(in).
+ *  - element type follows func_id: float for ids 0..18, double for 64..66,
+ *    complex float pairs for 80..82; n counts input elements.  sincosf
+ *    writes 2n floats, planar: out[0..n) = sin(in), out[n..2n) = cos(in).
  *  - n == 0 returns CR_OK without launching anything.
  *  - in == out (in place) is allowed for single-output functions; any other
  *    overlap of the input and output ranges is CR_E_OVERLAP.
@@ -49,7 +49,28 @@ enum cr_func {
   CR_ASINF = 13, CR_ACOSF = 14, CR_ATANF = 15,
   CR_SINHF = 16, CR_COSHF = 17, CR_TANHF = 18,
   CR_NUM_F32 = 19,
-  CR_EXP = 64, CR_LOG = 65 /* binary64 */
+  CR_EXP = 64, CR_LOG = 65, /* binary64 */
+  /* binary64 exp2 (paper, Sec. II-B): x = (4096 m + 256 i1 + 16 i2 + i3)/4096 + R,
+   * 2^x = 2^m T1[i1] T2[i2] T3[i3] 2^R with three 16-entry double-double tables */
+  CR_EXP2 = 66,
+  /* Complex binary32 functions accurate to 2 ulps on valid inputs, built from
+   * the correctly rounded real functions (the paper's second application
+   * benchmark, Sec. III-A).  Elements are complex numbers stored as
+   * interleaved (re, im) float pairs; n counts complex numbers; in and out
+   * need 4-byte alignment.  Each part is computed as stated, every correctly
+   * rounded ingredient bit-exact and every other step one IEEE operation:
+   *   cexpf: re = RN32(expf(x) cosf(y)), im = RN32(expf(x) sinf(y));
+   *          valid for finite x < 88.7 and finite y
+   *   csinf: re = RN32(sinf(x) coshf(y)), im = RN32(cosf(x) sinhf(y));
+   *          valid for finite x and |y| < 89.4
+   *   clogf: re = log|z| from logf or log1pf (near |z| = 1) plus a binary64
+   *          correction, im = atan2(y, x) from atanf(min/max) and binary64
+   *          reflections by pi/2 and pi; valid for finite z with
+   *          2^-63 <= |z| < 2^63 (below 1.5 ulps).
+   * Outside the valid inputs the results are those of the same IEEE
+   * operations (NaN signs and payloads unspecified).  CR_IMPL_AUTO or
+   * CR_IMPL_F64_INTERNAL only. */
+  CR_CEXPF = 80, CR_CLOGF = 81, CR_CSINF = 82
 };
 
 /* Implementation choice for the binary32 functions (paper, Sec. II-A: the
@@ -96,6 +117,26 @@ int cr_eval_ex(int func_id, int impl, unsigned flags, const void *in, void *out,
 /* 1 if func_id is provided with implementation impl (enum cr_impl) by this
  * build of the library, else 0. */
 int cr_available(int func_id, int impl);
+
+/* Spectral interpolation by a brute-force discrete Fourier transform of real
+ * samples (the paper's first application benchmark, Sec. III-A, which spends
+ * its time in sincosf): for k < m,
+ *   X[k] = sum_{j < n} x[j] (cos t_kj - i sin t_kj),  t_kj = RN32(w[k] j),
+ * with sinf/cosf of t_kj correctly rounded.  Each product x[j] cos t_kj is
+ * exact in binary64 and the sums are accumulated as double-doubles in a fixed
+ * order, so X[k] (re, im) is the binary64 rounding of a value within about
+ * n 2^-104 sum_j |x[j] cos t_kj| (resp. sin) of the exact sum, and the same on
+ * every run.  Device pointers: x (n floats), w (m floats: w[k] = 2 pi f_k / N
+ * for a frequency f_k in bins, any finite value allowed), X (m pairs of
+ * doubles, 16-byte aligned, caller-owned).  0 <= n <= 2^24 (sample indices
+ * exact in binary32; else CR_E_SIZE); m == 0 returns CR_OK.  flags: enum
+ * cr_flag.  X may not overlap x or w (CR_E_OVERLAP).  The call allocates and
+ * frees a stream-ordered workspace of m * S * 32 bytes (S = number of sample
+ * slices, at most n / 2048 + 1); asynchronous and stream-ordered like
+ * cr_eval.  Errors: CR_E_SIZE, CR_E_NULL, CR_E_ALIGN, CR_E_OVERLAP,
+ * CR_E_NOMEM, CR_E_HIP. */
+int cr_dft(const float *x, int64_t n, const float *w, int64_t m, double *X, unsigned flags,
+           void *stream);
 
 /* ------------------------------------------------------------------ batches
  * Many requests of mixed function and uneven length evaluated by ONE graph

@@ -23,14 +23,15 @@ def main():
     a = ap.parse_args()
     import torch
     from paper_2605_15547_amd import crmath, inputs
+    F64 = crmath.FUNCS64
     if not torch.cuda.is_available():
         raise SystemExit("autotune needs a GPU")
     crmath.tune_reset()
     sp = crmath._stream_ptr(None)
-    funcs = crmath.FUNCS32 + ["exp", "log"]
+    funcs = crmath.FUNCS32 + F64
     for f in funcs:
-        n = 1 << (a.log2n - 2 if f in ("exp", "log") else a.log2n)
-        x = inputs.workload_f64(f, n) if f in ("exp", "log") else inputs.workload_f32(f, n)
+        n = 1 << (a.log2n - 2 if f in F64 else a.log2n)
+        x = inputs.workload_f64(f, n) if f in F64 else inputs.workload_f32(f, n)
         xt = torch.from_numpy(x).cuda()
         out = torch.empty(2 * n if f == "sincosf" else n, dtype=xt.dtype, device="cuda")
         for impl in (crmath.IMPL_F64_INTERNAL, crmath.IMPL_SPLIT_F32):

@@ -16,6 +16,13 @@ FUNCS32 = ["expf", "exp2f", "exp10f", "expm1f", "logf", "log2f", "log10f", "log1
 FUNC_ID = {name: i for i, name in enumerate(FUNCS32)}
 FUNC_ID["exp"] = 64
 FUNC_ID["log"] = 65
+FUNC_ID["exp2"] = 66
+FUNCS64 = ["exp", "log", "exp2"]
+# complex binary32 functions (interleaved re, im pairs; n counts complex numbers)
+FUNC_ID["cexpf"] = 80
+FUNC_ID["clogf"] = 81
+FUNC_ID["csinf"] = 82
+COMPLEX = ["cexpf", "clogf", "csinf"]
 
 IMPL_AUTO, IMPL_F64_INTERNAL, IMPL_SPLIT_F32 = 0, 1, 2
 FLAG_FORCE_FALLBACK = 1
@@ -29,6 +36,7 @@ NOALLOC_MAX_TILES = 1 << 19
 
 EXPORTED = ["cr_eval", "cr_eval_ex", "cr_available", "cr_batch_plan_create",
             "cr_batch_plan_launch", "cr_batch_plan_destroy", "cr_eval_batch", "cr_eval_batch_noalloc",
+            "cr_dft",
             "cr_stats_reset",
             "cr_stats_read", "cr_status_str", "cr_last_hip_error", "cr_tune_num_variants",
             "cr_tune_variant_info", "cr_tune_get", "cr_tune_set", "cr_tune_reset", "cr_tune_load",
@@ -76,6 +84,8 @@ def lib():
         L.cr_eval_ex.restype = ctypes.c_int
         L.cr_available.argtypes = [ctypes.c_int, ctypes.c_int]
         L.cr_available.restype = ctypes.c_int
+        L.cr_dft.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, vp, ctypes.c_uint, vp]
+        L.cr_dft.restype = ctypes.c_int
         L.cr_batch_plan_create.argtypes = [ctypes.POINTER(Request), ctypes.c_int32, ctypes.c_uint,
                                            ctypes.POINTER(ctypes.c_void_p)]
         L.cr_batch_plan_launch.argtypes = [vp, vp]
@@ -124,18 +134,41 @@ def eval_ptr(func, in_ptr, out_ptr, n, impl=IMPL_AUTO, flags=0, stream_ptr=None)
 
 def evaluate(func, x, out=None, impl=IMPL_AUTO, flags=0, stream=None):
     """Correctly rounded func(x) for a contiguous CUDA tensor x (float32 for the
-    binary32 functions, float64 for exp/log).  sincosf returns shape (2, n)."""
+    binary32 functions, float64 for exp/log/exp2; complex functions take
+    interleaved (re, im) float32 pairs).  sincosf returns shape (2, n)."""
     import torch
     fid = _fid(func)
-    want = torch.float64 if fid >= 64 else torch.float32
+    want = torch.float64 if 64 <= fid < 80 else torch.float32
     if x.dtype != want or not x.is_cuda or not x.is_contiguous():
         raise ValueError("expected a contiguous CUDA %s tensor" % want)
-    n = x.numel()
-    nout = 2 * n if fid == FUNC_ID["sincosf"] else n
+    n = x.numel() // 2 if fid >= 80 else x.numel()
+    nout = 2 * n if fid == FUNC_ID["sincosf"] or fid >= 80 else n
     if out is None:
         out = torch.empty(nout, dtype=want, device=x.device)
     eval_ptr(fid, x.data_ptr(), out.data_ptr(), n, impl, flags, _stream_ptr(stream))
     return out.view(2, n) if fid == FUNC_ID["sincosf"] else out.view(x.shape)
+
+
+def dft_ptr(x_ptr, n, w_ptr, m, out_ptr, flags=0, stream_ptr=None):
+    """Raw cr_dft call: device pointers (ints), sample and frequency counts."""
+    rc = lib().cr_dft(ctypes.c_void_p(x_ptr), n, ctypes.c_void_p(w_ptr), m,
+                      ctypes.c_void_p(out_ptr), flags, stream_ptr)
+    if rc != CR_OK:
+        raise CrError(rc, "cr_dft")
+
+
+def dft(x, w, out=None, flags=0, stream=None):
+    """cr_dft on CUDA float32 tensors x (samples) and w (angles per output):
+    returns an (m, 2) float64 tensor of (re, im)."""
+    import torch
+    for t in (x, w):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("expected contiguous CUDA float32 tensors")
+    m = w.numel()
+    if out is None:
+        out = torch.empty((m, 2), dtype=torch.float64, device=w.device)
+    dft_ptr(x.data_ptr(), x.numel(), w.data_ptr(), m, out.data_ptr(), flags, _stream_ptr(stream))
+    return out
 
 
 def _requests(reqs):

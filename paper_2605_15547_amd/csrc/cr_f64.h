@@ -1,9 +1,9 @@
-// cr_f64.h -- correctly rounded binary64 exp and log (device).
+// cr_f64.h -- correctly rounded binary64 exp, exp2 and log (device).
 //
 // Paper, Sec. II-B: a highly accurate SIMD main path, a correct rounding
 // test, and a slower path for the lanes that fail it; the paper's cr_exp2
 // uses three 16-entry double-double tables and its cr_log one 128-entry
-// table.  This library provides exp and log with 16-entry tables only:
+// table.  Every table here has 16 entries:
 //
 // exp: k = nearest(x 256/ln2), r = x - k ln2/256 (four-part Cody-Waite,
 //   |r| <= ln2/512), k = 256 m + 16 i + j, e^x = 2^m T1[i] T2[j] e^r with
@@ -16,6 +16,12 @@
 //   double-double (TwoProd), log x = e' ln2 - ln c_j + log1p(t) with
 //   log1p t = t - t^2/2 + t^3/3 + t^4 S(t) (main path) or 2 atanh(t/(2+t))
 //   (accurate path).
+// exp2: the paper's own three-table design (Sec. II-B).  x = N/4096 + R with
+//   N = nearest(4096 x) and R = x - N/4096 exact (|R| <= 2^-13), N = 4096 m +
+//   256 i1 + 16 i2 + i3, 2^x = 2^m T1[i1] T2[i2] T3[i3] 2^R with the 16-entry
+//   tables T1 = 2^(i/16), T2 = 2^(i/256), T3 = 2^(i/4096) read as double-
+//   doubles by the main path, and 2^R = e^r, r = R ln2 (|r| <= 2^-13.53), by
+//   r + r^2 P(r) with P of degree 3.
 // The accurate path first tries a double-double middle path, which decides
 // all but the inputs within about 2^-42 ulp of a rounding boundary, and only
 // those take the triple-double evaluation.
@@ -33,11 +39,21 @@ struct Log64Tab {
   double c[16];
   double4 L[16];
 };
+struct Exp2_64Tab {
+  double4 t1[16], t2[16], t3[16];
+};
 
 __device__ __forceinline__ void exp64_tab_load(Exp64Tab& t, int tid) {
   if (tid < 16) {
     t.t1[tid] = EXP64_T1[tid];
     t.t2[tid] = EXP64_T2[tid];
+  }
+}
+__device__ __forceinline__ void exp2_64_tab_load(Exp2_64Tab& t, int tid) {
+  if (tid < 16) {
+    t.t1[tid] = EXP2_64_T1[tid];
+    t.t2[tid] = EXP2_64_T2[tid];
+    t.t3[tid] = EXP2_64_T3[tid];
   }
 }
 __device__ __forceinline__ void log64_tab_load(Log64Tab& t, int tid) {
@@ -168,6 +184,127 @@ __device__ __noinline__ AccResultD exp64_accurate(double x, const Exp64Tab& tb) 
   td T = td_mul(td_ld(tb.t1[(k >> 4) & 15]), td_ld(tb.t2[k & 15]));
   td y = td_add(T, td_mul(T, q));
   double e = fabs(y.h) * 0x1p-135;
+  bool ok;
+  double res;
+  if (m >= -1021) {
+    double c = round64_tail(y.h, y.m, y.l, e, ok);
+    res = scale_pow2(c, m);
+  } else {
+    double sc = pow2i(m + 1074 > -200 ? m + 1074 : -200);
+    double n = round_to_int(y.h * sc, y.m * sc, y.l * sc, e * sc, ok);
+    res = n * 0x1p-1074;
+  }
+  return {res, ok ? 1 : 0};
+}
+
+// ------------------------------------------------------------------ exp2
+// Branch-free: res is always written (meaningful only when true is returned).
+// 2^x rounds to +0 for x <= -1075 (x = -1075 is the midpoint between +0 and
+// the smallest subnormal and ties to +0), overflows for x >= 1024; NaN is
+// returned quieted.  Everything else goes through the evaluation, exact
+// powers of two included (y = 1 exactly, far from any rounding boundary).
+__device__ __forceinline__ bool exp2_64_special(double x, double& res) {
+  const bool nan = x != x;
+  const bool lo = x <= -1075.0, hi = x >= 1024.0;
+  res = nan ? __longlong_as_double(__double_as_longlong(x) | 0x0008000000000000ll)
+            : (hi ? INFINITY : 0.0);
+  return nan | lo | hi;
+}
+
+// The reduction shared by the three paths: N = nearest(4096 x) and the exact
+// remainder R = x - N/4096 (|x| <= 1076 after the clamp, so 4096 x and the
+// fma are exact and |N| < 2^23).
+struct Exp2Red {
+  double R;
+  int N;
+};
+__device__ __forceinline__ Exp2Red exp2_64_reduce(double x) {
+  double xc = fmin(fmax(x, -1076.0), 1025.0);
+  double nd = rint(xc * 4096.0);
+  return {fma(nd, -0x1p-12, xc), (int)nd};
+}
+
+// T1[i1] T2[i2] T3[i3] as a double-double (each factor to 2^-106, each
+// product 5u^2: within 2^-102.5 relative)
+__device__ __forceinline__ dd exp2_64_T(const Exp2_64Tab& tb, int N) {
+  double4 A = tb.t1[(N >> 8) & 15], B = tb.t2[(N >> 4) & 15], C = tb.t3[N & 15];
+  return dd_mul(dd_mul(dd{A.x, A.y}, dd{B.x, B.y}), dd{C.x, C.y});
+}
+
+// Main-path error, |r| <= 2^-13.53 (r^2 <= 2^-27.06, P ~ 1/2):
+//  * r = R ln2 as r.hi + r.lo: ln2 to 2^-107, the product error-free (fma),
+//    R ln2_lo rounded once: below 2^-119 absolute;
+//  * q = e^r - 1 = r.hi + (r.hi^2 P(r.hi) + r.lo): the rounding of r.hi^2
+//    times P (2^-81.06), P's Horner evaluation (relative 2^-52.4, times r^2/2:
+//    2^-80.5), the fma (half an ulp of a value below 2^-28: 2^-82), the term
+//    2 r.hi r.lo P left out of r^2 (2^-80.06) and P's approximation error
+//    (2^-91.95): below 2^-78.6 in all; the final Fast2Sum is exact;
+//  * T to 2^-102.5, T q (|q| < 2^-13.5) and T + T q in double-double: far
+//    below 2^-100 relative.
+// y = T e^r >= 2^-1/8192 carries at most 2^-78.5 relative; the test allows
+// 2^-77 |y|.
+constexpr double EXP2_64_EPS = 0x1p-77;
+
+__device__ __forceinline__ double exp2_64_fast(double x, const Exp2_64Tab& tb, bool& ok) {
+  Exp2Red k = exp2_64_reduce(x);
+  double rh = k.R * LN2_TD[0].x;
+  double rl = fma(k.R, LN2_TD[0].x, -rh) + k.R * LN2_TD[0].y;
+  double pp = EXP2_64_P[EXP2_64_P_DEG];
+#pragma unroll
+  for (int i = EXP2_64_P_DEG - 1; i >= 0; i--) pp = fma(pp, rh, EXP2_64_P[i]);
+  dd q = fast_two_sum(rh, fma(rh * rh, pp, rl));  // e^r - 1
+  dd T = exp2_64_T(tb, k.N);
+  dd y = dd_add_ord(T, dd_mul(T, q));  // in [2^-1/8192, 2)
+  double res = exp64_round(y, k.N >> 12, fabs(y.hi) * EXP2_64_EPS, ok);
+  double sp;
+  if (exp2_64_special(x, sp)) {
+    res = sp;
+    ok = true;
+  }
+  return res;
+}
+
+// Middle path (double-double): the main path's reduction and tables, e^r by
+// its Taylor series to degree 6 (remainder below 2^-106 for |r| <= 2^-13.53),
+// degrees 4..6 in binary64 as r^4 P inside the innermost step, 0..3 by
+// double-double Horner steps, r = R ln2 to 2^-119 absolute: y within 2^-100
+// relative; the test allows 2^-95.
+__device__ __forceinline__ double exp2_64_mid(double x, const Exp2_64Tab& tb, bool& ok) {
+  Exp2Red k = exp2_64_reduce(x);
+  dd r = dd_mul_d(dd{LN2_TD[0].x, LN2_TD[0].y}, k.R);
+  double P = fma(fma(INV_FACT[6].x, r.hi, INV_FACT[5].x), r.hi, INV_FACT[4].x);
+  dd w = dd_add_ord(dd{INV_FACT[3].x, INV_FACT[3].y}, dd{r.hi * P, 0.0});
+#pragma unroll
+  for (int i = 2; i >= 0; i--) w = dd_add_ord(dd{INV_FACT[i].x, INV_FACT[i].y}, dd_mul(r, w));
+  dd y = dd_mul(exp2_64_T(tb, k.N), w);
+  return exp64_round(y, k.N >> 12, fabs(y.hi) * 0x1p-95, ok);
+}
+
+__device__ __noinline__ AccResultD exp2_64_accurate(double x, const Exp2_64Tab& tb) {
+  double sp;
+  if (exp2_64_special(x, sp)) return {sp, 1};
+  bool mid_ok;
+  const double rm = exp2_64_mid(x, tb, mid_ok);
+  if (mid_ok) return {rm, 1};
+  // triple-double path: r = R ln2 (R exact, ln2 to 2^-159), e^r - 1 by its
+  // Taylor series to degree 10 (remainder below 2^-170), degrees 5.. in
+  // double-double, 1..4 in triple-double
+  Exp2Red k = exp2_64_reduce(x);
+  td r = td_mul_d(td_ld(LN2_TD[0]), k.R);
+  dd rd = {r.h, r.m};
+  dd ph = {INV_FACT[10].x, INV_FACT[10].y};
+#pragma unroll
+  for (int i = 9; i >= 5; i--) ph = dd_add(dd_mul(ph, rd), dd{INV_FACT[i].x, INV_FACT[i].y});
+  td pt = td_from_dd(ph);
+#pragma unroll
+  for (int i = 4; i >= 1; i--) pt = td_add(td_mul(pt, r), td_ld(INV_FACT_TD[i]));
+  td q = td_mul(pt, r);
+  const int N = k.N;
+  td T = td_mul(td_mul(td_ld(tb.t1[(N >> 8) & 15]), td_ld(tb.t2[(N >> 4) & 15])),
+                td_ld(tb.t3[N & 15]));
+  td y = td_add(T, td_mul(T, q));
+  double e = fabs(y.h) * 0x1p-135;
+  const int m = N >> 12;
   bool ok;
   double res;
   if (m >= -1021) {

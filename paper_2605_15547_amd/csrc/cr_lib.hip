@@ -646,6 +646,18 @@ struct OpLog64 {
   }
 };
 
+struct OpExp2_64 {
+  using Tab = Exp2_64Tab;
+  static constexpr int qcheck = QCHECK;
+  static __device__ __forceinline__ void load(Tab& t, int tid) { exp2_64_tab_load(t, tid); }
+  static __device__ __forceinline__ double fast(double x, const Tab& t, bool& ok) {
+    return exp2_64_fast(x, t, ok);
+  }
+  static __device__ __forceinline__ AccResultD accurate(double x, const Tab& t) {
+    return exp2_64_accurate(x, t);
+  }
+};
+
 struct Deferred64 {
   unsigned n, lanes, waves;
   unsigned idx[QCAP];
@@ -758,6 +770,283 @@ __global__ void __launch_bounds__(BLOCK)
     atomicAdd(&c.fallback_lanes, (unsigned long long)lanes);
     atomicAdd(&c.fallback_waves, 1ull);
   }
+}
+
+// ------------------------------------------------- application workloads
+// The paper's two synthetic applications built on the correctly rounded
+// binary32 functions (Sec. III-A): complex expf, logf and sinf accurate to
+// 2 ulps, and spectral interpolation by a brute-force DFT that spends its time
+// in sincosf.  Each correctly rounded ingredient is evaluated by its fast path
+// and, in a lane whose rounding test fails (rare on these workloads: no
+// hard-to-round inputs are planted), by its accurate path in place; the steps
+// between them are single IEEE operations in the stated formats.
+
+// One binary32 function, correctly rounded: fast path, accurate path if needed.
+struct LaneCount {
+  unsigned fails;
+  unsigned escapes;
+};
+template <class Op>
+__device__ __forceinline__ float cr1(float x, const typename Op::Tab& t, bool force, LaneCount& lc) {
+  bool ok;
+  float r = Op::fast(x, t, ok);
+  if (!ok || force) {
+    AccResult a = Op::accurate(x, t);
+    r = a.r;
+    lc.fails++;
+    lc.escapes += a.ok ? 0u : 1u;
+  }
+  return r;
+}
+__device__ __forceinline__ float cr_sincos(float x, const TrigTab& t, float& c, bool force,
+                                           LaneCount& lc) {
+  bool ok;
+  float s = sincos_fast(x, t, c, ok);
+  if (!ok || force) {
+    AccResult2 a = sincos_accurate(x, t);
+    s = a.s;
+    c = a.c;
+    lc.fails++;
+    lc.escapes += a.ok ? 0u : 1u;
+  }
+  return s;
+}
+
+// exp(x + iy) = e^x cos y + i e^x sin y: re = RN32(expf(x) cosf(y)),
+// im = RN32(expf(x) sinf(y)).  Each part is the correctly rounded product of
+// two correctly rounded factors: within 2 ulps.
+struct CExpF {
+  struct Tab {
+    ExpTab e;
+    TrigTab t;
+  };
+  static __device__ __forceinline__ void load(Tab& T, int tid) {
+    exp_tab_load(T.e, tid);
+    trig_tab_load(T.t, tid);
+  }
+  static __device__ __forceinline__ float2 eval(float x, float y, const Tab& T, bool force,
+                                                LaneCount& lc) {
+    const float E = cr1<OpExp<EXPK_E>>(x, T.e, force, lc);
+    float C;
+    const float S = cr_sincos(y, T.t, C, force, lc);
+    return make_float2(E * C, E * S);
+  }
+};
+
+// sin(x + iy) = sin x cosh y + i cos x sinh y, each product of correctly
+// rounded factors rounded once: within 2 ulps.
+struct CSinF {
+  struct Tab {
+    ExpTab e;
+    TrigTab t;
+  };
+  static __device__ __forceinline__ void load(Tab& T, int tid) {
+    exp_tab_load(T.e, tid);
+    trig_tab_load(T.t, tid);
+  }
+  static __device__ __forceinline__ float2 eval(float x, float y, const Tab& T, bool force,
+                                                LaneCount& lc) {
+    float C;
+    const float S = cr_sincos(x, T.t, C, force, lc);
+    const float Ch = cr1<OpHyp<HYPK_COSH>>(y, T.e, force, lc);
+    const float Sh = cr1<OpHyp<HYPK_SINH>>(y, T.e, force, lc);
+    return make_float2(S * Ch, C * Sh);
+  }
+};
+
+// log(x + iy) = log|z| + i atan2(y, x), valid for finite z with
+// 2^-63 <= |z| < 2^63.  With a = max(|x|, |y|), b = min(|x|, |y|):
+//  * imaginary part: A = atanf(RN32(b / a)) correctly rounded, then in
+//    binary64 v = A, v = RN64(pi/2) - v if |y| > |x|, v = RN64(pi) - v if
+//    x < 0; the result is RN32(v) with the sign of y (below 1.5 ulps: the
+//    quotient's rounding moves atan by at most 2^-24 t/(1 + t^2));
+//  * real part: s = RN64(a^2 + b^2) (the squares are exact in binary64).
+//    For 0.5 <= s < 2, d = RN64((a^2 - 1) + b^2) (a^2 - 1 exact), d = dh + dl
+//    with dh = RN32(d) and dl exact, and log|z| = (log1pf(dh) + dl/(1 + dh))/2;
+//    otherwise s = sh + sl, sh = RN32(s), and log|z| = (logf(sh) + sl/sh)/2,
+//    the correction term's second-order error being below 2^-46 relative:
+//    below 1.5 ulps.
+struct CLogF {
+  struct Tab {
+    AtanTab a;
+    LogTab l;
+  };
+  static __device__ __forceinline__ void load(Tab& T, int tid) {
+    atan_tab_load(T.a, tid);
+    log_tab_load<LOGK_E>(T.l, tid);  // logf and log1pf share the natural-log table
+  }
+  static __device__ __forceinline__ float2 eval(float x, float y, const Tab& T, bool force,
+                                                LaneCount& lc) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float a = fmaxf(ax, ay), b = fminf(ax, ay);
+    const float A = cr1<OpAtan<ATANK_ATAN>>(b / a, T.a, force, lc);
+    double v = (double)A;
+    if (ay > ax) v = 0x1.921fb54442d18p+0 - v;  // RN64(pi/2) - v
+    if (x < 0.0f) v = 0x1.921fb54442d18p+1 - v;  // RN64(pi) - v
+    const float im = copysignf((float)v, y);
+    const double a2 = (double)a * (double)a, b2 = (double)b * (double)b;
+    const double s = a2 + b2;
+    double re;
+    if (s >= 0.5 && s < 2.0) {
+      const double d = (a2 - 1.0) + b2;
+      const float dh = (float)d;
+      const double dl = d - (double)dh;
+      const float L = cr1<OpLog<LOGK_1P>>(dh, T.l, force, lc);
+      re = 0.5 * ((double)L + dl / (1.0 + (double)dh));
+    } else {
+      const float sh = (float)s;
+      const double sl = s - (double)sh;
+      const float L = cr1<OpLog<LOGK_E>>(sh, T.l, force, lc);
+      re = 0.5 * ((double)L + sl / (double)sh);
+    }
+    return make_float2((float)re, im);
+  }
+};
+
+// Complex map: interleaved (re, im) binary32 pairs, two complex numbers per
+// 128-bit load and store.  Persistent grid, tables staged in LDS.
+template <class CF>
+__global__ void __launch_bounds__(BLOCK)
+    k_complex(const float4* in, float4* out, long long n2, DevStats* st, unsigned flags,
+              long long elem_base) {
+  __shared__ typename CF::Tab tab;
+  __shared__ unsigned fails;
+  CF::load(tab, threadIdx.x);
+  if (threadIdx.x == 0) fails = 0;
+  __syncthreads();
+  const bool force = flags & CR_FLAG_FORCE_FALLBACK;
+  LaneCount tot = {0u, 0u};
+  for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n2;
+       i += (long long)gridDim.x * BLOCK) {
+    const float4 v = ld_stream(in + i);
+    LaneCount lc = {0u, 0u};
+    const float2 r0 = CF::eval(v.x, v.y, tab, force, lc);
+    if (lc.escapes) note_escape(st, elem_base + 2 * i);
+    tot.fails += lc.fails;
+    lc = {0u, 0u};
+    const float2 r1 = CF::eval(v.z, v.w, tab, force, lc);
+    if (lc.escapes) note_escape(st, elem_base + 2 * i + 1);
+    tot.fails += lc.fails;
+    st_stream(out + i, make_float4(r0.x, r0.y, r1.x, r1.y));
+  }
+  if (tot.fails) atomicAdd(&fails, tot.fails);
+  __syncthreads();
+  if (threadIdx.x == 0 && fails) {
+    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
+    atomicAdd(&c.fallback_lanes, (unsigned long long)fails);
+    atomicAdd(&c.fallback_waves, 1ull);
+  }
+}
+
+// Scalar form for unaligned buffers and a ragged last element (4-byte loads).
+template <class CF>
+__global__ void __launch_bounds__(BLOCK)
+    k_complex_scalar(const float* in, float* out, long long n, DevStats* st, unsigned flags,
+                     long long elem_base) {
+  __shared__ typename CF::Tab tab;
+  CF::load(tab, threadIdx.x);
+  __syncthreads();
+  const bool force = flags & CR_FLAG_FORCE_FALLBACK;
+  unsigned fails = 0;
+  for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n;
+       i += (long long)gridDim.x * BLOCK) {
+    LaneCount lc = {0u, 0u};
+    const float2 r = CF::eval(in[2 * i], in[2 * i + 1], tab, force, lc);
+    if (lc.escapes) note_escape(st, elem_base + i);
+    fails += lc.fails;
+    out[2 * i] = r.x;
+    out[2 * i + 1] = r.y;
+  }
+  if (fails) {
+    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
+    atomicAdd(&c.fallback_lanes, (unsigned long long)fails);
+    atomicAdd(&c.fallback_waves, 1ull);
+  }
+}
+
+// Brute-force DFT of real samples at per-output angles (spectral
+// interpolation): X_k = sum_n x[n] (cos t - i sin t), t = RN32(w_k n), with
+// sincosf correctly rounded.  Each product x[n] cos t is exact in binary64;
+// the sums are carried as double-doubles (TwoSum per term), so X_k is within
+// about N 2^-104 sum |x c| of the exact sum of the exact products before its
+// final rounding.  Block (s, k) covers samples [s L, (s + 1) L) of output k
+// and writes its partial sums (re.hi, re.lo, im.hi, im.lo); a second kernel
+// adds the S partials of each k in a fixed order, so results do not depend
+// on timing.
+__device__ __forceinline__ void dd_acc(double& hi, double& lo, double p) {
+  const dd t = two_sum(hi, p);
+  hi = t.hi;
+  lo += t.lo;
+}
+__device__ __forceinline__ void dd_acc2(double& hi, double& lo, double h2, double l2) {
+  const dd t = two_sum(hi, h2);
+  const dd u = fast_two_sum(t.hi, t.lo + (lo + l2));
+  hi = u.hi;
+  lo = u.lo;
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    k_dft(const float* x, long long n, const float* w, long long slice, double4* part, int S,
+          DevStats* st, unsigned flags, long long k0) {
+  __shared__ TrigTab tab;
+  __shared__ double4 red[BLOCK / 64];
+  __shared__ unsigned fails;
+  trig_tab_load(tab, threadIdx.x);
+  if (threadIdx.x == 0) fails = 0;
+  __syncthreads();
+  const bool force = flags & CR_FLAG_FORCE_FALLBACK;
+  const long long k = blockIdx.y;
+  const float wk = w[k];
+  const long long n0 = (long long)blockIdx.x * slice;
+  const long long n1 = n0 + slice < n ? n0 + slice : n;
+  double rh = 0.0, rl = 0.0, ih = 0.0, il = 0.0;
+  LaneCount lc = {0u, 0u};
+  for (long long i = n0 + threadIdx.x; i < n1; i += BLOCK) {
+    const float th = wk * (float)i;  // RN32(w_k n), n < 2^24 exact
+    float c;
+    const float s = cr_sincos(th, tab, c, force, lc);
+    const double xd = (double)x[i];
+    dd_acc(rh, rl, xd * (double)c);
+    dd_acc(ih, il, xd * (double)s);
+  }
+  if (lc.escapes) note_escape(st, k0 + k);
+  // wave reduction in a fixed order (xor butterfly), then across the 4 waves
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double a = __shfl_xor(rh, off), b = __shfl_xor(rl, off);
+    const double c = __shfl_xor(ih, off), d = __shfl_xor(il, off);
+    dd_acc2(rh, rl, a, b);
+    dd_acc2(ih, il, c, d);
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_double4(rh, rl, ih, il);
+  if (lc.fails) atomicAdd(&fails, lc.fails);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double4 acc = red[0];
+    for (int q = 1; q < BLOCK / 64; q++) {
+      dd_acc2(acc.x, acc.y, red[q].x, red[q].y);
+      dd_acc2(acc.z, acc.w, red[q].z, red[q].w);
+    }
+    part[k * S + blockIdx.x] = acc;
+    if (fails) {
+      CounterSlot& cs = st->slot[(blockIdx.y * gridDim.x + blockIdx.x) % NSLOT];
+      atomicAdd(&cs.fallback_lanes, (unsigned long long)fails);
+      atomicAdd(&cs.fallback_waves, 1ull);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(BLOCK)
+    k_dft_finish(const double4* part, int S, long long m, double2* X) {
+  const long long k = (long long)blockIdx.x * BLOCK + threadIdx.x;
+  if (k >= m) return;
+  double4 acc = part[k * S];
+  for (int q = 1; q < S; q++) {
+    const double4 p = part[k * S + q];
+    dd_acc2(acc.x, acc.y, p.x, p.y);
+    dd_acc2(acc.z, acc.w, p.z, p.w);
+  }
+  X[k] = make_double2(acc.x + acc.y, -(acc.z + acc.w));
 }
 
 // ------------------------------------------------------------ ragged batch
@@ -1222,8 +1511,54 @@ int launch_map_f64(const double* in, double* out, size_t n, hipStream_t s, unsig
   return CR_OK;
 }
 
-bool func_valid(int f) { return (f >= 0 && f < CR_NUM_F32) || f == CR_EXP || f == CR_LOG; }
-bool func_built(int f) { return (f >= CR_EXPF && f <= CR_TANHF) || f == CR_EXP || f == CR_LOG; }
+// Complex binary32 map (n complex numbers, interleaved): 16-byte aligned
+// body of two complex numbers per vector, scalar head and tail.
+template <class CF>
+int launch_complex(const float* in, float* out, size_t n, hipStream_t s, unsigned flags,
+                   DevStats* st, int grid) {
+  uintptr_t ai = (uintptr_t)in, ao = (uintptr_t)out;
+  size_t head = 0;
+  if ((ai & 15) == (ao & 15) && (ai & 7) == 0) {
+    head = (ai & 15) ? 1 : 0;
+    if (head > n) head = n;
+  } else {
+    head = n;
+  }
+  const size_t body2 = (n - head) / 2;
+  const size_t tail = n - head - 2 * body2;
+  auto scalar = [&](size_t off, size_t cnt) {
+    size_t g = (cnt + BLOCK - 1) / BLOCK;
+    if (g > (size_t)grid) g = grid;
+    hipLaunchKernelGGL(k_complex_scalar<CF>, dim3((unsigned)g), dim3(BLOCK), 0, s, in + 2 * off,
+                       out + 2 * off, (long long)cnt, st, flags, (long long)off);
+  };
+  if (head) scalar(0, head);
+  for (size_t done = 0; done < body2;) {
+    size_t chunk = body2 - done;
+    if (chunk > ((size_t)1 << 30)) chunk = (size_t)1 << 30;
+    size_t g = (chunk + BLOCK - 1) / BLOCK;
+    if (g > (size_t)grid) g = grid;
+    const size_t off = head + 2 * done;
+    hipLaunchKernelGGL(k_complex<CF>, dim3((unsigned)g), dim3(BLOCK), 0, s,
+                       reinterpret_cast<const float4*>(in + 2 * off),
+                       reinterpret_cast<float4*>(out + 2 * off), (long long)chunk, st, flags,
+                       (long long)off);
+    done += chunk;
+  }
+  if (tail) scalar(head + 2 * body2, tail);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e);
+  return CR_OK;
+}
+
+bool func_complex(int f) { return f == CR_CEXPF || f == CR_CLOGF || f == CR_CSINF; }
+bool func_f64(int f) { return f == CR_EXP || f == CR_LOG || f == CR_EXP2; }
+bool func_valid(int f) { return (f >= 0 && f < CR_NUM_F32) || func_f64(f) || func_complex(f); }
+bool func_built(int f) {
+  return (f >= CR_EXPF && f <= CR_TANHF) || func_f64(f) || func_complex(f);
+}
+// bytes of one input element (complex: two binary32) and of the output per element
+size_t elem_bytes(int f) { return func_f64(f) || func_complex(f) ? 8 : 4; }
 // functions with a binary32-only (split) implementation
 bool split_built(int f) { return f >= CR_EXPF && f <= CR_TANHF; }
 
@@ -1284,12 +1619,18 @@ int dispatch_f32(int f, const float* in, float* out, size_t n, hipStream_t s, un
 // One launch configuration per (implementation, function): a k_map_f32
 // variant and the persistent grid in workgroups per compute unit.  Index 0 of
 // the first dimension is the binary64-internal implementation (and AUTO), 1
-// the split one; functions 0..18, then exp (19) and log (20).
-constexpr int NFUNC_IDX = CR_NUM_F32 + 2;
+// the split one; functions 0..18, then the ids of EXTRA_FUNCS.
+constexpr int EXTRA_FUNCS[] = {CR_EXP, CR_LOG, CR_EXP2, CR_CEXPF, CR_CLOGF, CR_CSINF};
+constexpr int NFUNC_IDX = CR_NUM_F32 + (int)(sizeof(EXTRA_FUNCS) / sizeof(EXTRA_FUNCS[0]));
 std::atomic<int> g_cfg_variant[2][NFUNC_IDX];
 std::atomic<int> g_cfg_bpc[2][NFUNC_IDX];  // 0: the default
 
-int fidx(int f) { return f < CR_NUM_F32 ? f : (f == CR_EXP ? CR_NUM_F32 : CR_NUM_F32 + 1); }
+int fidx(int f) {
+  if (f < CR_NUM_F32) return f;
+  for (int i = 0; i < NFUNC_IDX - CR_NUM_F32; i++)
+    if (EXTRA_FUNCS[i] == f) return CR_NUM_F32 + i;
+  return 0;  // not reached: callers validate f first
+}
 int iidx(int impl) { return impl == CR_IMPL_SPLIT_F32 ? 1 : 0; }
 // sincos and the binary64 functions have one kernel shape (variant 0 only)
 int num_variants_of(int f) { return (f == CR_SINCOSF || f >= 64) ? 1 : NVARIANT; }
@@ -1306,6 +1647,14 @@ int eval_cfg(int func_id, int impl, unsigned flags, const void* in, void* out, s
     rc = dispatch_f32(func_id, (const float*)in, (float*)out, n, s, flags, st, variant, g);
   else if (func_id == CR_EXP)
     rc = launch_map_f64<OpExp64>((const double*)in, (double*)out, n, s, flags, st, g);
+  else if (func_id == CR_EXP2)
+    rc = launch_map_f64<OpExp2_64>((const double*)in, (double*)out, n, s, flags, st, g);
+  else if (func_id == CR_CEXPF)
+    rc = launch_complex<CExpF>((const float*)in, (float*)out, n, s, flags, st, g);
+  else if (func_id == CR_CLOGF)
+    rc = launch_complex<CLogF>((const float*)in, (float*)out, n, s, flags, st, g);
+  else if (func_id == CR_CSINF)
+    rc = launch_complex<CSinF>((const float*)in, (float*)out, n, s, flags, st, g);
   else
     rc = launch_map_f64<OpLog64>((const double*)in, (double*)out, n, s, flags, st, g);
   if (rc == CR_OK) {
@@ -1319,9 +1668,9 @@ int eval_cfg(int func_id, int impl, unsigned flags, const void* in, void* out, s
 const char* const FUNC_NAMES[NFUNC_IDX] = {
     "expf", "exp2f", "exp10f", "expm1f", "logf", "log2f", "log10f", "log1pf", "rsqrtf",
     "sinf", "cosf", "sincosf", "tanf", "asinf", "acosf", "atanf", "sinhf", "coshf", "tanhf",
-    "exp", "log"};
+    "exp", "log", "exp2", "cexpf", "clogf", "csinf"};
 
-int func_of_idx(int i) { return i < CR_NUM_F32 ? i : (i == CR_NUM_F32 ? CR_EXP : CR_LOG); }
+int func_of_idx(int i) { return i < CR_NUM_F32 ? i : EXTRA_FUNCS[i - CR_NUM_F32]; }
 
 // ------------------------------------------------------------ batch plans
 }  // namespace
@@ -1501,11 +1850,11 @@ int cr_eval_ex(int func_id, int impl, unsigned flags, const void* in, void* out,
     return CR_E_IMPL;
   if (n == 0) return CR_OK;
   if (!in || !out) return CR_E_NULL;
-  const size_t es = func_id >= 64 ? 8 : 4;
+  const size_t es = elem_bytes(func_id), al = func_complex(func_id) ? 4 : es;
   const size_t nout = func_id == CR_SINCOSF ? 2 * n : n;
   if (n > ((size_t)1 << 60)) return CR_E_SIZE;
   uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
-  if ((a % es) || (b % es)) return CR_E_ALIGN;
+  if ((a % al) || (b % al)) return CR_E_ALIGN;
   bool same = a == b && nout == n;
   if (!same && a < b + nout * es && b < a + n * es) return CR_E_OVERLAP;
   if (!cr_available(func_id, impl)) return CR_E_IMPL;
@@ -1626,11 +1975,11 @@ int cr_autotune(int func_id, int impl, const void* in, void* out, size_t n, int 
   if (impl != CR_IMPL_AUTO && impl != CR_IMPL_F64_INTERNAL && impl != CR_IMPL_SPLIT_F32)
     return CR_E_IMPL;
   if (n == 0 || !in || !out) return CR_E_NULL;
-  const size_t es = func_id >= 64 ? 8 : 4;
+  const size_t es = elem_bytes(func_id), al = func_complex(func_id) ? 4 : es;
   const size_t nout = func_id == CR_SINCOSF ? 2 * n : n;
   if (n > ((size_t)1 << 60)) return CR_E_SIZE;
   uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
-  if ((a % es) || (b % es)) return CR_E_ALIGN;
+  if ((a % al) || (b % al)) return CR_E_ALIGN;
   bool same = a == b && nout == n;
   if (!same && a < b + nout * es && b < a + n * es) return CR_E_OVERLAP;
   if (!cr_available(func_id, impl)) return CR_E_IMPL;
@@ -1713,6 +2062,51 @@ int cr_available(int func_id, int impl) {
 
 int cr_eval(int func_id, const void* in, void* out, size_t n, void* stream) {
   return cr_eval_ex(func_id, CR_IMPL_AUTO, 0u, in, out, n, stream);
+}
+
+int cr_dft(const float* x, int64_t n, const float* w, int64_t m, double* X, unsigned flags,
+           void* stream) {
+  if (n < 0 || m < 0 || n > ((int64_t)1 << 24) || m > ((int64_t)1 << 31)) return CR_E_SIZE;
+  if (m == 0) return CR_OK;
+  if (!w || !X || (n > 0 && !x)) return CR_E_NULL;
+  if (((uintptr_t)x % 4) || ((uintptr_t)w % 4) || ((uintptr_t)X % 16)) return CR_E_ALIGN;
+  const uintptr_t xo = (uintptr_t)X, xe = xo + (uintptr_t)m * 16;
+  if ((n > 0 && (uintptr_t)x < xe && xo < (uintptr_t)x + (uintptr_t)n * 4) ||
+      ((uintptr_t)w < xe && xo < (uintptr_t)w + (uintptr_t)m * 4))
+    return CR_E_OVERLAP;
+  DevStats* st = nullptr;
+  int rc = get_stats(&st);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  // samples per block: enough blocks to fill the chip (8 per CU) but at least
+  // 8 samples per thread
+  const long long target = (long long)num_cus() * 8;
+  long long S = (target + m - 1) / m;
+  const long long smax = (n + BLOCK * 8 - 1) / (BLOCK * 8);
+  if (S > smax) S = smax;
+  if (S < 1) S = 1;
+  long long slice = (n + S - 1) / S;
+  slice = (slice + BLOCK - 1) / BLOCK * BLOCK;
+  if (slice < BLOCK) slice = BLOCK;
+  S = n > 0 ? (n + slice - 1) / slice : 1;
+  double4* part = nullptr;
+  hipError_t e = hipMallocAsync((void**)&part, (size_t)m * S * sizeof(double4), s);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? CR_E_NOMEM : hip_fail(e);
+  for (long long k0 = 0; k0 < m; k0 += 65535) {  // grid.y is at most 65535
+    const long long mk = m - k0 < 65535 ? m - k0 : 65535;
+    hipLaunchKernelGGL(k_dft, dim3((unsigned)S, (unsigned)mk), dim3(BLOCK), 0, s, x,
+                       (long long)n, w + k0, slice, part + k0 * S, (int)S, st, flags, k0);
+  }
+  hipLaunchKernelGGL(k_dft_finish, dim3((unsigned)((m + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s,
+                     part, (int)S, (long long)m, reinterpret_cast<double2*>(X));
+  e = hipGetLastError();
+  hipError_t e2 = hipFreeAsync(part, s);
+  if (e != hipSuccess) return hip_fail(e);
+  if (e2 != hipSuccess) return hip_fail(e2);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  g_elems[dev] += (unsigned long long)n * (unsigned long long)m;
+  return CR_OK;
 }
 
 

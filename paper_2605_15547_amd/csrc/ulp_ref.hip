@@ -22,7 +22,7 @@ typedef double v2d_t __attribute__((ext_vector_type(2)));
 enum {
   F_EXPF = 0, F_EXP2F, F_EXP10F, F_EXPM1F, F_LOGF, F_LOG2F, F_LOG10F, F_LOG1PF, F_RSQRTF,
   F_SINF, F_COSF, F_SINCOSF, F_TANF, F_ASINF, F_ACOSF, F_ATANF, F_SINHF, F_COSHF, F_TANHF,
-  F_EXP = 64, F_LOG = 65
+  F_EXP = 64, F_LOG = 65, F_EXP2 = 66
 };
 
 template <int F>
@@ -93,7 +93,9 @@ __global__ void __launch_bounds__(BLOCK) k_ref64(const double2* in, double2* out
       long long i = t * BLOCK * 2 * U + u * BLOCK + threadIdx.x;
       if (i < n2) {
         v2d_t v = __builtin_nontemporal_load(reinterpret_cast<const v2d_t*>(in + i));
-        v2d_t r = F == F_EXP ? v2d_t{exp(v.x), exp(v.y)} : v2d_t{log(v.x), log(v.y)};
+        v2d_t r = F == F_EXP    ? v2d_t{exp(v.x), exp(v.y)}
+                  : F == F_EXP2 ? v2d_t{exp2(v.x), exp2(v.y)}
+                                : v2d_t{log(v.x), log(v.y)};
         __builtin_nontemporal_store(r, reinterpret_cast<v2d_t*>(out + i));
       }
     }
@@ -150,10 +152,11 @@ extern "C" int cr_ref_eval(int f, const void* in, void* out, size_t n, void* str
                          reinterpret_cast<float4*>(b + n), n4);
       break;
     case F_EXP:
+    case F_EXP2:
     case F_LOG: {
       if (n % 2) return -1;
       long long n2 = (long long)(n / 2);
-      auto k = f == F_EXP ? k_ref64<F_EXP> : k_ref64<F_LOG>;
+      auto k = f == F_EXP ? k_ref64<F_EXP> : (f == F_EXP2 ? k_ref64<F_EXP2> : k_ref64<F_LOG>);
       hipLaunchKernelGGL(k, dim3(grid_for(n2 / 2)), dim3(BLOCK), 0, s,
                          reinterpret_cast<const double2*>(in), reinterpret_cast<double2*>(out),
                          n2);

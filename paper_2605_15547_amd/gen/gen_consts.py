@@ -306,6 +306,18 @@ def gen_trig():
     emit_const("PI32_MID", m1)
     emit_const("PI32_LO", l)
     emit_const("PI64", d(mp.pi / 64), "pi/64 (small-argument threshold)")
+    # Cody-Waite form of the reduction for |x| < 2^23 (|k| < 2^26.4): pi/32 in
+    # three parts, the first on 26 bits so that k CW1 is exact
+    with mp.workprec(800):
+        c = mp.pi / 32
+        c1 = split_bits(c, 26)
+        rem = c - mp.mpf(c1)
+        c2 = float(rem)
+        c3 = float(rem - mp.mpf(c2))
+    emit_const("PI32_CW1", c1, "pi/32 rounded to 26 bits")
+    emit_const("PI32_CW2", c2)
+    emit_const("PI32_CW3", c3)
+    emit_const("INV_PI32", d(32 / mp.pi), "32/pi")
     emit("// sin(j pi/32), cos(j pi/32) for j = 0..15, double-double: {s_hi, s_lo, c_hi, c_lo}")
     emit("__device__ __constant__ const double4 SINCOS_T[16] = {")
     for j in range(16):
@@ -459,6 +471,34 @@ def gen_f64():
     emit("#define LOG64_S_DEG %d" % (len(cd) - 1))
     emit("#define ATANH64_N 16")
     emit_dd_table("INV_ODD_DD", [mp.mpf(1) / (2 * k + 1) for k in range(17)], "1/(2k+1), k = 0..16")
+    emit()
+    gen_exp2_64()
+
+
+def gen_exp2_64():
+    """binary64 exp2 (paper, Sec. II-B): 2^x = 2^m T1[i1] T2[i2] T3[i3] 2^R with
+    x = (4096 m + 256 i1 + 16 i2 + i3)/4096 + R, |R| <= 2^-13, and three
+    16-entry tables: the main path reads each entry as a double-double
+    (hi, mid); the third word serves the accurate path."""
+    emit("// ---- binary64 exp2 ----")
+    with mp.workprec(600):
+        for name, den in (("EXP2_64_T1", 16), ("EXP2_64_T2", 256), ("EXP2_64_T3", 4096)):
+            emit_td_table(name, [mp.power(2, mp.mpf(i) / den) for i in range(16)],
+                          "2^(i/%d) as triple-double {hi, mid, lo, 0}" % den)
+    # e^r - 1 - r = r^2 P(r) on |r| <= ln2 / 8192 (r = R ln2)
+    rho = mp.log(2) / 8192 * mp.mpf("1.0001")
+    for deg in range(1, 6):
+        cs = lawson_fit(lambda r: (mp.expm1(r) - r) / (r * r) if r != 0 else mp.mpf(0.5),
+                        lambda r: r * r, -rho, rho, list(range(deg + 1)), npts=80, iters=12)
+        cd = [d(v) for v in cs]
+        err = max_err(lambda r: mp.expm1(r) - r - r * r * sum(mp.mpf(cd[k]) * r ** k
+                                                              for k in range(len(cd))), -rho, rho)
+        if err < mp.mpf(2) ** -88:
+            break
+    emit("// e^r - 1 = r + r^2 P(r), |r| <= ln2/8192; |error| <= 2^%.2f (absolute, proven)"
+         % log2_of(B.sup_bound(B.expm1_minus_r([mp.mpf(v) for v in cd], rho))))
+    emit_arr("EXP2_64_P", cd, "coefficients (degree %d)" % (len(cd) - 1))
+    emit("#define EXP2_64_P_DEG %d" % (len(cd) - 1))
     emit()
 
 

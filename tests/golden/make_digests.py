@@ -14,7 +14,7 @@ Targets (one JSON file each under tests/golden/digests/):
   expf_correctness          64 specials/edges + 2^20 uniform in [-103.9, 88.7]
   explog_2p26.<func>        exp/log family, 2^26 elements per function
   trig_2p26.<func>          trig/inverse/hyperbolic family, 2^26 per function
-  binary64_2p24.<func>      binary64 exp/log, 2^24 elements per function
+  binary64_2p24.<func>      binary64 exp/log/exp2, 2^24 elements per function
   batch_4096                the 4096-request ragged batch, one digest per request
   exhaustive.<func>         all 2^32 binary32 encodings of expf, logf, sinf
                             (paper, Sec. II-A: binary32 functions are validated
@@ -207,7 +207,7 @@ def main():
         elif tg == "trig":
             t_family("trig_2p26", I.TRIG_FAMILY, a.threads)
         elif tg == "binary64":
-            t_family("binary64_2p24", ["exp", "log"], a.threads)
+            t_family("binary64_2p24", ["exp", "log", "exp2"], a.threads)
         elif tg == "batch":
             if not exists("batch_4096"):
                 t_batch(a.threads)

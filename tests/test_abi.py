@@ -47,7 +47,7 @@ def test_argument_validation(L):
     # n == 0: nothing to do
     assert ev(0, 0, 0, None, None, 0, None) == C.CR_OK
     # unknown function ids
-    for f in (-1, 19, 63, 66, 1000):
+    for f in (-1, 19, 63, 67, 79, 83, 1000):
         assert ev(f, 0, 0, vp(0x1000), vp(0x2000), 8, None) == -1
     # null pointers
     assert ev(0, 0, 0, None, vp(0x2000), 8, None) == -2
@@ -62,6 +62,31 @@ def test_argument_validation(L):
     assert ev(0, 7, 0, vp(0x1000), vp(0x2000), 8, None) == -5
     assert L.cr_available(0, 7) == 0
     assert L.cr_available(99, 0) == 0
+    # binary64 exp2 takes 8-byte elements
+    assert ev(66, 0, 0, vp(0x1004), vp(0x2000), 8, None) == -4
+    # complex functions: float pairs, 4-byte alignment, no binary32-only form
+    assert ev(80, 0, 0, vp(0x1002), vp(0x2000), 8, None) == -4
+    assert ev(81, 0, 0, vp(0x1000), vp(0x1008), 8, None) == -3  # 8 pairs = 64 bytes
+    assert ev(82, 2, 0, vp(0x1000), vp(0x2000), 8, None) == -5
+    for f in (80, 81, 82, 66):
+        assert L.cr_available(f, 0) == 1
+        assert L.cr_available(f, 2) == 0
+
+
+def test_dft_validation(L):
+    """cr_dft rejects bad arguments before launching anything."""
+    vp = ctypes.c_void_p
+    d = L.cr_dft
+    assert d(vp(0x1000), 8, vp(0x2000), 0, vp(0x3000), 0, None) == 0   # m == 0
+    assert d(vp(0x1000), (1 << 24) + 1, vp(0x2000), 4, vp(0x3000), 0, None) == -9
+    assert d(vp(0x1000), -1, vp(0x2000), 4, vp(0x3000), 0, None) == -9
+    assert d(None, 8, vp(0x2000), 4, vp(0x3000), 0, None) == -2
+    assert d(vp(0x1000), 8, None, 4, vp(0x3000), 0, None) == -2
+    assert d(vp(0x1000), 8, vp(0x2000), 4, None, 0, None) == -2
+    assert d(vp(0x1000), 8, vp(0x2000), 4, vp(0x3008), 0, None) == -4
+    assert d(vp(0x1002), 8, vp(0x2000), 4, vp(0x3000), 0, None) == -4
+    assert d(vp(0x3010), 8, vp(0x2000), 4, vp(0x3000), 0, None) == -3  # x inside X
+    assert d(vp(0x1000), 8, vp(0x3030), 4, vp(0x3000), 0, None) == -3  # w inside X
 
 
 def test_batch_validation(L):

@@ -28,6 +28,8 @@ import make_digests as MD  # noqa: E402
 
 from paper_2605_15547_amd import crmath, inputs  # noqa: E402
 
+F64 = crmath.FUNCS64
+
 DIG = os.path.join(HERE, "golden", "digests")
 IMPLS = [("f64", crmath.IMPL_F64_INTERNAL), ("split", crmath.IMPL_SPLIT_F32)]
 TUNING = os.path.join(os.path.dirname(HERE), "paper_2605_15547_amd", "tuning", "mi355x.txt")
@@ -58,7 +60,7 @@ def _load(name):
 
 def _gpu_eval(func, xt, impl):
     n = xt.numel()
-    dt = torch.float64 if func in ("exp", "log") else torch.float32
+    dt = torch.float64 if func in F64 else torch.float32
     out = torch.empty(2 * n if func == "sincosf" else n, dtype=dt, device="cuda")
     crmath.eval_ptr(func, xt.data_ptr(), out.data_ptr(), n, impl, 0, crmath._stream_ptr(None))
     return out
@@ -76,7 +78,7 @@ def _explain(func, x, y, blocks, block=MD.BLOCK):
     xs = x[b * block:(b + 1) * block]
     ref = O.evaluate(func, xs)
     got = y[:, b * block:(b + 1) * block] if func == "sincosf" else y[b * block:(b + 1) * block]
-    ib = np.uint64 if func in ("exp", "log") else np.uint32
+    ib = np.uint64 if func in F64 else np.uint32
     gb, rb = np.asarray(got).view(ib).ravel(), np.asarray(ref).view(ib).ravel()
     bad = np.nonzero(gb != rb)[0]
     if not bad.size:
@@ -122,7 +124,7 @@ def test_trig_family_2p26_digest(func, impl):
     _check_array("trig_2p26." + func, func, inputs.workload_f32(func, 1 << 26), impl[1])
 
 
-@pytest.mark.parametrize("func", ["exp", "log"])
+@pytest.mark.parametrize("func", F64)
 def test_binary64_2p24_digest(func):
     _need_gpu()
     _check_array("binary64_2p24." + func, func, inputs.workload_f64(func, 1 << 24),

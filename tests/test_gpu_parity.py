@@ -13,6 +13,8 @@ torch = pytest.importorskip("torch")
 
 from paper_2605_15547_amd import crmath, inputs  # noqa: E402
 
+F64 = crmath.FUNCS64
+
 F32 = crmath.FUNCS32
 
 
@@ -28,7 +30,7 @@ def built(func, impl=crmath.IMPL_AUTO):
 def gpu_eval(func, x, impl=crmath.IMPL_AUTO, flags=0, offset_in=0, offset_out=0):
     """Run func on the GPU; offsets shift the device pointers by whole elements
     to exercise unaligned heads."""
-    dt = torch.float64 if func in ("exp", "log") else torch.float32
+    dt = torch.float64 if func in F64 else torch.float32
     n = x.size
     nout = 2 * n if func == "sincosf" else n
     xin = torch.empty(n + offset_in, dtype=dt, device="cuda")
@@ -58,12 +60,12 @@ def assert_same(func, x, got, ref):
 
 
 def workload(func, n, seed=None):
-    if func in ("exp", "log"):
+    if func in F64:
         return inputs.workload_f64(func, n, seed)
     return inputs.workload_f32(func, n, seed)
 
 
-ALL = F32 + ["exp", "log"]
+ALL = F32 + F64
 
 
 @pytest.mark.parametrize("func", ALL)
@@ -90,7 +92,7 @@ def test_unaligned_pointers_and_in_place(oracle, func):
     for oi, oo in ((1, 1), (1, 0), (0, 3), (2, 2)):
         assert_same(func, x, gpu_eval(func, x, offset_in=oi, offset_out=oo), ref)
     if func != "sincosf":
-        dt = torch.float64 if func in ("exp", "log") else torch.float32
+        dt = torch.float64 if func in F64 else torch.float32
         t = torch.from_numpy(x).to("cuda", dt)
         crmath.eval_ptr(func, t.data_ptr(), t.data_ptr(), x.size, 0, 0, crmath._stream_ptr(None))
         torch.cuda.synchronize()
@@ -136,12 +138,15 @@ def test_special_inputs(oracle, func):
     _need_gpu()
     if not built(func):
         pytest.skip("not built")
-    if func in ("exp", "log"):
+    if func in F64:
         sp = np.array([0.0, -0.0, np.inf, -np.inf, 1.0, -1.0, 5e-324, -5e-324,
                        2.2250738585072014e-308, 1.7976931348623157e308, -1.7976931348623157e308,
                        709.782712893384, 709.7827128933841, -745.1332191019411,
                        -745.1332191019412, -708.3964185322641, 2.0 ** -53, 1 + 2.0 ** -52,
-                       1 - 2.0 ** -53], dtype=np.float64)
+                       1 - 2.0 ** -53, 1024.0, np.nextafter(1024.0, 0), -1074.0, -1075.0,
+                       np.nextafter(-1075.0, 0), np.nextafter(-1075.0, -np.inf), -1022.0,
+                       np.nextafter(-1022.0, 0), -1074.5, 0.5, -0.5, 2.0 ** -1022 * 3],
+                      dtype=np.float64)
         nanb = np.array([0x7FF8000000000000, 0xFFF8000000000000, 0x7FF0000000000001,
                          0x7FF8000000012345], dtype=np.uint64)
         sp = np.concatenate([sp, nanb.view(np.float64)])
@@ -175,7 +180,7 @@ def test_full_size_sampled(oracle, func):
     _need_gpu()
     if not built(func):
         pytest.skip("not built")
-    n = (1 << 24) if func in ("exp", "log") else (1 << 26)
+    n = (1 << 24) if func in F64 else (1 << 26)
     x = workload(func, n)
     got = gpu_eval(func, x)
     idx = inputs.Stream(424242).below(1 << 14, n)
@@ -187,13 +192,13 @@ def test_full_size_sampled(oracle, func):
         assert_same(func, xs, got[idx], ref)
 
 
-@pytest.mark.parametrize("func", ["exp", "log"])
+@pytest.mark.parametrize("func", F64)
 def test_binary64_main_path_matches_accurate_path(func):
     """binary64 has no exhaustive check: on 2^25 inputs (the workload and
-    uniformly random encodings of the domain) every result the main path
-    certifies must equal the accurate path's, forced on every element.  With
-    a main-path test of width 2^-69 (exp) or 2^-65 (log) relative, a few
-    thousand of these inputs lie within the test's width of a rounding
+    uniformly random values or encodings of the domain) every result the main
+    path certifies must equal the accurate path's, forced on every element.
+    With a main-path test of width 2^-69 (exp), 2^-70 (log) or 2^-77 (exp2)
+    relative, some of these inputs lie within the test's width of a rounding
     boundary, where an understated error bound would show."""
     _need_gpu()
     n = 1 << 24
@@ -201,6 +206,8 @@ def test_binary64_main_path_matches_accurate_path(func):
     st = inputs.Stream(78)
     if func == "exp":
         xs.append((-745.0 + (709.7 + 745.0) * st.uniform(n)).astype(np.float64))
+    elif func == "exp2":
+        xs.append((-1075.0 + (1024.0 + 1075.0) * st.uniform(n)).astype(np.float64))
     else:
         b = (st.u64(n) >> np.uint64(1)) % np.uint64(0x7FF0000000000000)
         xs.append(b.view(np.float64))
@@ -211,3 +218,50 @@ def test_binary64_main_path_matches_accurate_path(func):
         assert crmath.stats_read()["escapes"] == 0
         bad = np.nonzero(bits(a) != bits(b))[0]
         assert bad.size == 0, (func, bad.size, hex(int(bits(x)[bad[0]])))
+
+
+def test_exp2_exact_and_tie_cases(oracle):
+    """binary64 exp2 at every integer k in [-1080, 1030] (2^k exactly, +0 at
+    and below the tie -1075, +Inf from 1024 on), at k + 1/2, k + 1/4, k + 3/4
+    and at k +- 1 ulp, against the oracle."""
+    _need_gpu()
+    k = np.arange(-1080, 1031, dtype=np.float64)
+    x = np.concatenate([k, k + 0.5, k + 0.25, k + 0.75, np.nextafter(k, np.inf),
+                        np.nextafter(k, -np.inf)])
+    crmath.stats_reset()
+    got = gpu_eval("exp2", x)
+    assert_same("exp2", x, got, oracle.evaluate("exp2", x))
+    assert crmath.stats_read()["escapes"] == 0
+
+
+def _edge_inputs(func):
+    """Encodings around the function's regime edges (overflow, underflow, first
+    subnormal result, saturation, last f(x) == x or 1), located with the oracle
+    (tests/golden/func_edges.json, written by tests/golden/make_func_edges.py)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "func_edges.json")
+    with open(path) as f:
+        doc = json.load(f)["functions"][func]
+    ut, ft = (np.uint64, np.float64) if func in F64 else (np.uint32, np.float32)
+    b = [int(v, 16) for e in doc for v in e["bits"]]
+    return np.array(b, dtype=ut).view(ft)
+
+
+@pytest.mark.parametrize("impl", [crmath.IMPL_F64_INTERNAL, crmath.IMPL_SPLIT_F32],
+                         ids=["f64", "split"])
+@pytest.mark.parametrize("func", ALL)
+def test_function_edges(oracle, func, impl):
+    """Every function at its regime edges, +-2 encodings, in both
+    implementations; with the accurate path forced as well."""
+    _need_gpu()
+    if func in F64 and impl == crmath.IMPL_SPLIT_F32:
+        pytest.skip("binary64 functions have one implementation")
+    if not built(func, impl):
+        pytest.skip("not built")
+    x = _edge_inputs(func)
+    ref = oracle.evaluate(func, x)
+    crmath.stats_reset()
+    assert_same(func, x, gpu_eval(func, x, impl=impl), ref)
+    assert_same(func, x, gpu_eval(func, x, impl=impl, flags=crmath.FLAG_FORCE_FALLBACK), ref)
+    assert crmath.stats_read()["escapes"] == 0

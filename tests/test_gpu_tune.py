@@ -10,6 +10,8 @@ torch = pytest.importorskip("torch")
 
 from paper_2605_15547_amd import crmath, inputs  # noqa: E402
 
+F64 = crmath.FUNCS64
+
 from test_gpu_parity import assert_same, gpu_eval  # noqa: E402
 
 
@@ -52,7 +54,7 @@ def test_every_variant_is_bit_exact(oracle, func, impl):
 def test_autotune_installs_a_correct_configuration(oracle, func, impl):
     _need_gpu()
     n = 1 << 20
-    if func in ("exp", "log"):
+    if func in F64:
         x = inputs.workload_f64(func, n, seed=32_000)
         dt = torch.float64
     else:
