@@ -42,6 +42,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FAMILY = ["expf", "exp2f", "exp10f", "expm1f", "logf", "log2f", "log10f", "log1pf", "rsqrtf"]
 TRIG = ["sinf", "cosf", "sincosf", "tanf", "asinf", "acosf", "atanf", "sinhf", "coshf", "tanhf"]
+OTHER_LEGS = ("trig", "binary64", "vsulp", "complex", "dft", "batch", "split")
 
 
 def bytes_per_elem(func):
@@ -383,6 +384,9 @@ def main():
                                                       "mi355x.txt"),
                     help="launch configurations written by paper_2605_15547_amd/autotune.py")
     ap.add_argument("--no-tuning", action="store_true", help="library default configurations")
+    ap.add_argument("--only", default=None,
+                    help="comma-separated subset of the other workloads to measure: "
+                         + ",".join(OTHER_LEGS) + " (default: all)")
     ap.add_argument("--headline-only", action="store_true",
                     help="measure only the exp/log-family step (profiling runs)")
     ap.add_argument("--copy-ref", action="store_true",
@@ -485,30 +489,37 @@ def main():
         copy_ms = e0.elapsed_time(e1) / a.steps
 
     extra = {}
+    legs = set(OTHER_LEGS if a.only is None else a.only.split(","))
     if not a.headline_only:
         # free the headline buffers, then measure the other workloads
         del xs, outs
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
-        extra["trig_hyperbolic_family"] = bench_family(
-            torch, crmath, inputs, TRIG, n, a.impl, a.steps, a.warmup, stream)
-        extra["binary64_exp_log"] = bench_family(
-            torch, crmath, inputs, list(F64), 1 << 24, 0, a.steps, a.warmup, stream)
-        extra["vs_ulp_library"] = bench_vs_ulp(torch, crmath, inputs, n, a.steps, a.warmup,
-                                               stream)
-        extra["complex_functions"] = bench_complex(torch, crmath, inputs, 1 << 24, a.steps,
-                                                   a.warmup, stream)
-        extra["spectral_interpolation_dft"] = bench_dft(torch, crmath, inputs, 1 << 20, 256,
-                                                        a.steps, a.warmup, stream)
-        extra["ragged_batch"] = bench_batch(torch, crmath, inputs, a.steps, a.warmup, stream)
-        extra["ragged_batch_split_f32"] = bench_batch(torch, crmath, inputs, a.steps, a.warmup,
-                                                      stream, impl=2)
-        # the binary32-only (float-float) implementation beside the binary64-internal one
-        extra["exp_log_family_split_f32"] = bench_family(
-            torch, crmath, inputs, FAMILY, n, 2, a.steps, a.warmup, stream)
-        extra["trig_hyperbolic_family_split_f32"] = bench_family(
-            torch, crmath, inputs, TRIG, n, 2, a.steps, a.warmup,
-            stream)
+        if "trig" in legs:
+            extra["trig_hyperbolic_family"] = bench_family(
+                torch, crmath, inputs, TRIG, n, a.impl, a.steps, a.warmup, stream)
+        if "binary64" in legs:
+            extra["binary64_exp_log"] = bench_family(
+                torch, crmath, inputs, list(F64), 1 << 24, 0, a.steps, a.warmup, stream)
+        if "vsulp" in legs:
+            extra["vs_ulp_library"] = bench_vs_ulp(torch, crmath, inputs, n, a.steps, a.warmup,
+                                                   stream)
+        if "complex" in legs:
+            extra["complex_functions"] = bench_complex(torch, crmath, inputs, 1 << 24, a.steps,
+                                                       a.warmup, stream)
+        if "dft" in legs:
+            extra["spectral_interpolation_dft"] = bench_dft(torch, crmath, inputs, 1 << 20, 256,
+                                                            a.steps, a.warmup, stream)
+        if "batch" in legs:
+            extra["ragged_batch"] = bench_batch(torch, crmath, inputs, a.steps, a.warmup, stream)
+            extra["ragged_batch_split_f32"] = bench_batch(torch, crmath, inputs, a.steps,
+                                                          a.warmup, stream, impl=2)
+        if "split" in legs:
+            # the binary32-only (float-float) implementation beside the binary64-internal one
+            extra["exp_log_family_split_f32"] = bench_family(
+                torch, crmath, inputs, FAMILY, n, 2, a.steps, a.warmup, stream)
+            extra["trig_hyperbolic_family_split_f32"] = bench_family(
+                torch, crmath, inputs, TRIG, n, 2, a.steps, a.warmup, stream)
 
     cpu, parity = None, None
     if not a.no_cpu_baseline:

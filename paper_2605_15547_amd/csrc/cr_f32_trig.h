@@ -83,6 +83,36 @@ __device__ __forceinline__ Reduced payne_hanek(uint32_t ax, const unsigned* w) {
   return R;
 }
 
+// The fast path's form of the same reduction: only the 96 leading bits of the
+// window (W0, W1, W2), so P' = M (W >> 64) takes three multiply-adds instead
+// of five.  P' is bits 64.. of P less the carry of M (W mod 2^64) < 2^88 out
+// of the dropped low part, i.e. less than 2^-66 in units of N; the 64
+// fraction bits of f (bits 153..90 of P) come out low by at most one unit of
+// 2^-64 (the high word R.fhi only; R.flo is not formed).
+__device__ __forceinline__ Reduced payne_hanek_fast(uint32_t ax, const unsigned* w) {
+  int E = (int)(ax >> 23) - 150;
+  E = E < -28 ? -28 : (E > 105 ? 105 : E);
+  uint32_t M = (ax & 0x007fffffu) | 0x00800000u;
+  int sp = E - 2 + 32;
+  int wi = sp >> 5, sh = 32 - (sp & 31);
+  uint32_t t0 = w[wi], t1 = w[wi + 1], t2 = w[wi + 2], t3 = w[wi + 3];
+  uint32_t W0 = (uint32_t)((((uint64_t)t0 << 32) | t1) >> sh);
+  uint32_t W1 = (uint32_t)((((uint64_t)t1 << 32) | t2) >> sh);
+  uint32_t W2 = (uint32_t)((((uint64_t)t2 << 32) | t3) >> sh);
+  uint64_t a = (uint64_t)M * W2;
+  uint32_t p2 = (uint32_t)a;
+  a = (uint64_t)M * W1 + (a >> 32);
+  uint32_t p3 = (uint32_t)a;
+  a = (uint64_t)M * W0 + (a >> 32);
+  uint32_t p4 = (uint32_t)a;
+  uint64_t F = ((uint64_t)(p4 & 0x03ffffffu) << 38) | ((uint64_t)p3 << 6) | (p2 >> 26);
+  Reduced R;
+  R.q = (int)(((p4 >> 26) + (uint32_t)(F >> 63)) & 63);
+  R.fhi = (long long)F;
+  R.flo = 0;
+  return R;
+}
+
 // sin/cos of theta = q pi/32 as double-doubles, from the table and the quadrant
 struct SinCosTheta {
   double sh, sl, ch, cl;
@@ -126,13 +156,35 @@ __device__ __forceinline__ TrigFast trig_fast_core(float xf, const TrigTab& tb) 
   uint32_t ax = f32_bits(xf) & 0x7fffffffu;
   double axd = (double)bits_f32(ax);
   bool small = axd < PI64;
-  Reduced R = payne_hanek(ax, tb.w);
-  // f = fhi 2^-64 (+ flo 2^-128, ignored here: < 2^-64), as the exact sum of
-  // its signed high and unsigned low 32-bit halves
-  double fh = (double)(int)(R.fhi >> 32) * 0x1p-32;
-  double fl = (double)(uint32_t)R.fhi * 0x1p-64;
-  double r = fma(fh, PI32_HI, fma(fh, PI32_MID, fl * PI32_HI));
-  int q = R.q;
+  double r;
+  int q;
+  // The one branch of the method is on the size of the argument (the paper
+  // keeps Payne-Hanek for large arguments only): when every lane of the wave
+  // has |x| < 2^23, the wave takes a Cody-Waite reduction in binary64
+  // instead, k = nearest(|x| 32/pi) (|k| < 2^26.4), r = ((|x| - k C1) - k C2)
+  // - k C3 with C1 on 26 bits (k C1 exact, and |x| - k C1 exact: a multiple
+  // of 2^-29 below 2^-4) and k C2 as an exact product: r within
+  // 2^-53 |r| + 2^-105 of |x| - k pi/32 (the final addition's rounding and
+  // the terms below 2^-57), inside the bound below.  The branch is
+  // wave-uniform, so it costs no divergence; the result is certified by the
+  // same test either way, so it does not depend on which branch runs.
+  if (__all(ax < 0x4b000000u)) {
+    const double kd = rint(axd * INV_PI32);
+    const double r1 = fma(-kd, PI32_CW1, axd);
+    const dd p = two_prod(kd, PI32_CW2);
+    const dd t = two_sum(r1, -p.hi);
+    r = t.hi + (fma(-kd, PI32_CW3, t.lo) - p.lo);
+    q = (int)kd & 63;
+  } else {
+    Reduced R = payne_hanek_fast(ax, tb.w);
+    // f = fhi 2^-64 (the reduction leaves it low by less than 2^-64; the bits
+    // below are not formed), as the exact sum of its signed high and
+    // unsigned low 32-bit halves
+    double fh = (double)(int)(R.fhi >> 32) * 0x1p-32;
+    double fl = (double)(uint32_t)R.fhi * 0x1p-64;
+    r = fma(fh, PI32_HI, fma(fh, PI32_MID, fl * PI32_HI));
+    q = R.q;
+  }
   if (small) {
     r = axd;
     q = 0;
@@ -151,7 +203,8 @@ __device__ __forceinline__ TrigFast trig_fast_core(float xf, const TrigTab& tb) 
   o.s = th.sh + (th.sl + fma(th.sh, cm1, th.ch * sr));
   o.c = th.ch + (th.cl + fma(th.ch, cm1, -(th.sh * sr)));
   // Error bounds: r is within 2^-52 |r| + 2^-66 of f pi/32 after reduction
-  // (exact when |x| < pi/64); the polynomials are within 2^-66; the sums add
+  // (f within 2^-63 in units of N, times pi/32: 2^-66.35; r exact when
+  // |x| < pi/64); the polynomials are within 2^-66; the sums add
   // a few units of 2^-53 |result| (|sin x|, |cos x| >= 0.049 unless j = 0, in
   // which case the table terms are exact).  Bound: 2^-49 |y| + 2^-63.
   double abs_term = small ? 0.0 : 0x1p-63;

@@ -11,13 +11,21 @@ from collections import defaultdict
 
 FUNCS = {"OpExp<0>": "expf", "OpExp<1>": "exp2f", "OpExp<2>": "exp10f", "OpExp<3>": "expm1f",
          "OpLog<0>": "logf", "OpLog<1>": "log2f", "OpLog<2>": "log10f", "OpLog<3>": "log1pf",
-         "OpRsqrt": "rsqrtf"}
+         "OpRsqrt": "rsqrtf", "OpTrig<0>": "sinf", "OpTrig<1>": "cosf", "OpTrig<2>": "tanf",
+         "SinCosF64": "sincosf", "OpAtan<0>": "atanf", "OpAtan<1>": "asinf",
+         "OpAtan<2>": "acosf", "OpHyp<0>": "sinhf", "OpHyp<1>": "coshf", "OpHyp<2>": "tanhf",
+         "OpExp64": "exp", "OpLog64": "log", "OpExp2_64": "exp2", "CExpF": "cexpf",
+         "CLogF": "clogf", "CSinF": "csinf"}
+for _k in list(FUNCS):
+    if _k.startswith("Op") and not _k.endswith("64") and _k[2:3] != "S":
+        FUNCS["OpS" + _k[2:]] = FUNCS[_k] + " split"
+FUNCS["SinCosSplit"] = "sincosf split"
 
 
 def short(name):
     """k_map_f32<OpLog<3>> (log1pf) style names for the library's kernels."""
     name = name.replace("(anonymous namespace)::", "")
-    m = re.match(r"void (k_\w+)<(\w+(?:<\d+>)?) ?>", name)
+    m = re.match(r"void (k_\w+)<(\w+(?:<\d+>)?)[ ,>]", name)
     if m:
         op = m.group(2)
         return "%s<%s> (%s)" % (m.group(1), op, FUNCS.get(op, "?"))
@@ -43,9 +51,9 @@ def counter(db):
     for r in db.execute(q):
         d = dict(zip(cols, r))
         agg[(short(d.get("kernel_name", "?")), d.get("counter_name"))].append(d.get("value"))
-    print("%-44s %-12s %6s %14s" % ("kernel", "counter", "calls", "avg_per_dispatch"))
+    print("%-44s %-20s %6s %16s" % ("kernel", "counter", "calls", "avg_per_dispatch"))
     for (k, c), v in sorted(agg.items()):
-        print("%-44s %-12s %6d %14.1f" % (k, c, len(v), sum(v) / len(v)))
+        print("%-44s %-20s %6d %16.1f" % (k, c, len(v), sum(v) / len(v)))
 
 
 if __name__ == "__main__":
