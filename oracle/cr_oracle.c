@@ -7,6 +7,9 @@
  *
  * Definition followed (paper, Sec. I; Sec. II-A, validation paragraph): the
  * correctly rounded result is RN_even(f(x)) of the exact real value f(x).
+ * cr_oracle_eval_mode also gives the results in the directed rounding modes
+ * the paper's CPU library supports (Sec. II-A: round toward zero, up, down):
+ * the same enclosures, with both ends rounded in that mode.
  * Method (paper, Sec. I, Ziv's iterative approach): enclose f(x) in an
  * interval; if both ends round to the same floating-point number, that number
  * is the answer; otherwise double the precision and try again.
@@ -988,21 +991,37 @@ static int ev(int kind, double x, int p, ball *y, int64_t *e2) {
 }
 
 /* --------------------------- final rounding --------------------------- */
+/* Rounding mode of the current evaluation (IEEE 754-2019, Sec. 4.3):
+ * 0 = to nearest, ties to even; 1 = toward zero; 2 = toward +infinity;
+ * 3 = toward -infinity. */
+enum { RM_RN = 0, RM_RZ = 1, RM_RU = 2, RM_RD = 3 };
+static __thread int t_mode = RM_RN;
+
+/* The result of an overflow (Sec. 7.4): infinity when the mode rounds away
+ * from zero in the result's direction (or to nearest), else the largest
+ * finite number. */
+static uint64_t overflow_enc(int fmt, int neg) {
+  const uint64_t sign = neg ? (fmt ? (uint64_t)1 << 63 : (uint64_t)1 << 31) : 0;
+  const uint64_t inf = fmt ? 0x7ff0000000000000ull : 0x7f800000ull;
+  const uint64_t max = inf - 1;
+  int to_inf = t_mode == RM_RN || (t_mode == RM_RU && !neg) || (t_mode == RM_RD && neg);
+  return sign | (to_inf ? inf : max);
+}
+
 /* Round the exact real value M * 2^s (M an unsigned magnitude) to binary32
- * (fmt 0) or binary64 (fmt 1), round to nearest, ties to even, with gradual
- * underflow and overflow to infinity (IEEE 754-2019, Sec. 4.3.1, 7.4).
+ * (fmt 0) or binary64 (fmt 1) in the current rounding mode, with gradual
+ * underflow and overflow as above (IEEE 754-2019, Sec. 4.3.1, 4.3.2, 7.4).
  * If dist is non-null it receives the distance of the value from the
- * nearest rounding boundary, in units of the result's quantum. */
+ * nearest round-to-nearest boundary, in units of the result's quantum. */
 static uint64_t round_mag(const uint64_t *M, int64_t s, int fmt, int neg, double *dist) {
   const int P = fmt ? 53 : 24;
   const int emin = fmt ? -1022 : -126, emax = fmt ? 1023 : 127, bias = fmt ? 1023 : 127;
   const uint64_t sign = neg ? (fmt ? (uint64_t)1 << 63 : (uint64_t)1 << 31) : 0;
-  const uint64_t inf = fmt ? 0x7ff0000000000000ull : 0x7f800000ull;
   int nb = w_bitlen(M);
   if (dist) *dist = 0.5;
   if (nb == 0) return sign;
   int64_t E = nb - 1 + s; /* exponent of the leading bit */
-  if (E > emax) return sign | inf;
+  if (E > emax) return overflow_enc(fmt, neg);
   int64_t q = (E < emin ? emin : E) - (P - 1); /* exponent of the quantum */
   int64_t sh = q - s;                          /* bits below the quantum */
   uint64_t mant;
@@ -1022,7 +1041,11 @@ static uint64_t round_mag(const uint64_t *M, int64_t s, int fmt, int neg, double
       *dist = ldexp((double)diff, -take);
       if (diff == 0 && w_anybelow(M, sh - take)) *dist = ldexp(1.0, -take - 1);
     }
-    if (rbit && (sticky || (mant & 1))) mant++;
+    if (t_mode == RM_RN) {
+      if (rbit && (sticky || (mant & 1))) mant++;
+    } else if (rbit || sticky) { /* inexact: step away from zero if the mode says so */
+      if ((t_mode == RM_RU && !neg) || (t_mode == RM_RD && neg)) mant++;
+    }
   }
   if (mant == ((uint64_t)1 << P)) {
     mant >>= 1;
@@ -1031,7 +1054,7 @@ static uint64_t round_mag(const uint64_t *M, int64_t s, int fmt, int neg, double
   uint64_t enc;
   if (mant >> (P - 1)) {
     int64_t ex = q + P - 1;
-    if (ex > emax) return sign | inf;
+    if (ex > emax) return overflow_enc(fmt, neg);
     enc = ((uint64_t)(ex + bias) << (P - 1)) | (mant & (((uint64_t)1 << (P - 1)) - 1));
   } else {
     enc = mant; /* subnormal */
@@ -1092,10 +1115,21 @@ static int round_ball(const ball *y, int64_t e2, int fmt, uint64_t *enc, double 
  * domain errors; exact zero results; the one exact midpoint exp2f(-150)).
  * Also cheap saturation bounds where the result is certainly an infinity,
  * a zero or +-1.  Returns 1 when the result is decided. */
+/* The rounding of +-(1 - d) for 0 < d below a quarter of an ulp of 1:
+ * +-1 to nearest, else 1 or its predecessor by the mode. */
+static uint64_t below_one(int fmt, int neg) {
+  const uint64_t one = fmt ? ONE64 : ONE32, sign = neg ? (fmt ? NEG64 : NEG32) : 0;
+  int mag_one = t_mode == RM_RN || (t_mode == RM_RU && !neg) || (t_mode == RM_RD && neg);
+  return sign | (mag_one ? one : one - 1);
+}
+
+/* The rounding of a positive value below half the smallest subnormal: +0,
+ * or the smallest subnormal when rounding up. */
+static uint64_t tiny_positive(void) { return t_mode == RM_RU ? 1 : 0; }
+
 static int special(int kind, int fmt, double x, uint64_t *r) {
   const uint64_t one = fmt ? ONE64 : ONE32, inf = fmt ? INF64 : INF32,
                  qnan = fmt ? QNAN64 : QNAN32, neg = fmt ? NEG64 : NEG32;
-  const uint64_t negone = one | neg;
   int sn = signbit(x) != 0;
   uint64_t szero = sn ? neg : 0; /* signed zero like x */
   switch (kind) {
@@ -1113,18 +1147,18 @@ static int special(int kind, int fmt, double x, uint64_t *r) {
       else if (kind == K_EXP) { hiT = 100; loT = -110; }
       else if (kind == K_EXP2) { hiT = 128; loT = -151; }
       else { hiT = 40; loT = -47; }
-      if (x >= hiT) { *r = inf; return 1; }
-      if (x <= loT) { *r = 0; return 1; }
+      if (x >= hiT) { *r = overflow_enc(fmt, 0); return 1; }
+      if (x <= loT) { *r = tiny_positive(); return 1; }
       /* binary32: 2^-150 is exactly the midpoint between 0 and 2^-149 (ties
        * to even give +0); in binary64 it is an ordinary representable value */
-      if (!fmt && kind == K_EXP2 && x == -150) { *r = 0; return 1; }
+      if (!fmt && kind == K_EXP2 && x == -150) { *r = tiny_positive(); return 1; }
       return 0;
     }
     case K_EXPM1:
       if (x == 0) { *r = szero; return 1; }
-      if (isinf(x)) { *r = x > 0 ? inf : negone; return 1; }
-      if (x >= 100) { *r = inf; return 1; }
-      if (x <= -40) { *r = negone; return 1; }
+      if (isinf(x)) { *r = x > 0 ? inf : (one | neg); return 1; }
+      if (x >= 100) { *r = overflow_enc(fmt, 0); return 1; }
+      if (x <= -40) { *r = below_one(fmt, 1); return 1; }
       return 0;
     case K_LOG:
     case K_LOG2:
@@ -1167,15 +1201,82 @@ static int special(int kind, int fmt, double x, uint64_t *r) {
       return 0; /* +-inf: +-RN(pi/2) from the Ziv loop */
     case K_SINH:
       if (x == 0) { *r = szero; return 1; }
-      if (isinf(x) || fabs(x) >= 100) { *r = inf | (sn ? neg : 0); return 1; }
+      if (isinf(x)) { *r = inf | (sn ? neg : 0); return 1; }
+      if (fabs(x) >= 100) { *r = overflow_enc(fmt, sn); return 1; }
       return 0;
     case K_COSH:
       if (x == 0) { *r = one; return 1; }
-      if (isinf(x) || fabs(x) >= 100) { *r = inf; return 1; }
+      if (isinf(x)) { *r = inf; return 1; }
+      if (fabs(x) >= 100) { *r = overflow_enc(fmt, 0); return 1; }
       return 0;
     case K_TANH:
       if (x == 0) { *r = szero; return 1; }
-      if (isinf(x) || fabs(x) >= 50) { *r = sn ? negone : one; return 1; }
+      if (isinf(x)) { *r = sn ? (one | neg) : one; return 1; }
+      if (fabs(x) >= 50) { *r = below_one(fmt, sn); return 1; }
+      return 0;
+  }
+  return 0;
+}
+
+/* Non-special inputs whose result is a representable number (the only ones:
+ * the exact values of exp2 at integers, exp10 at 1..10, log2 at powers of 2,
+ * log10 at 10..10^10, rsqrt at powers of 4; every other finite result of
+ * these functions at a non-zero algebraic argument is transcendental).  In a
+ * directed mode an enclosure of such a value always straddles it, so the Ziv
+ * loop could not finish; the exact value is returned instead.  (To nearest,
+ * the Ziv loop decides them: an exact value is never a midpoint.) */
+static int exact_case(int kind, int fmt, double x, uint64_t *r) {
+  static const double P10[11] = {1e0, 1e1, 1e2, 1e3, 1e4, 1e5, 1e6, 1e7, 1e8, 1e9, 1e10};
+  int e;
+  double m;
+  switch (kind) {
+    case K_EXP2:
+      if (x != nearbyint(x)) return 0;
+      e = (int)x;
+      if (!fmt) {
+        if (e < -149 || e > 127) return 0;
+        *r = e >= -126 ? (uint64_t)(e + 127) << 23 : (uint64_t)1 << (e + 149);
+      } else {
+        if (e < -1074 || e > 1023) return 0;
+        *r = e >= -1022 ? (uint64_t)(e + 1023) << 52 : (uint64_t)1 << (e + 1074);
+      }
+      return 1;
+    case K_EXP10:
+      if (fmt || x != nearbyint(x) || x < 1 || x > 10) return 0;
+      {
+        float v = (float)P10[(int)x]; /* 10^k < 2^34 with at most 24 significant bits */
+        uint32_t b;
+        memcpy(&b, &v, 4);
+        *r = b;
+      }
+      return 1;
+    case K_LOG2:
+    case K_RSQRT:
+      if (!(x > 0) || isinf(x)) return 0;
+      m = frexp(x, &e); /* x = m 2^e, m in [1/2, 1) */
+      if (m != 0.5) return 0;
+      e -= 1; /* x = 2^e */
+      if (kind == K_RSQRT) {
+        if (e & 1) return 0;
+        e = -e / 2; /* rsqrt(2^(2k)) = 2^-k, a normal binary32 number */
+        *r = (uint64_t)(e + 127) << 23;
+      } else {
+        float v = (float)e; /* exact: |e| <= 149 */
+        uint32_t b;
+        memcpy(&b, &v, 4);
+        *r = b;
+      }
+      return 1;
+    case K_LOG10:
+      if (fmt) return 0;
+      for (int k = 1; k <= 10; k++)
+        if (x == P10[k]) {
+          float v = (float)k;
+          uint32_t b;
+          memcpy(&b, &v, 4);
+          *r = b;
+          return 1;
+        }
       return 0;
   }
   return 0;
@@ -1186,7 +1287,7 @@ static __thread int t_maxp = 0;
 
 /* Returns 1 and the encoding on success; 0 if unresolved below PMAX. */
 static int ziv(int kind, int fmt, double x, uint64_t *enc, double *hard) {
-  if (special(kind, fmt, x, enc)) {
+  if (special(kind, fmt, x, enc) || (t_mode != RM_RN && exact_case(kind, fmt, x, enc))) {
     if (hard) *hard = 0;
     return 1;
   }
@@ -1264,12 +1365,13 @@ typedef struct {
   void *out;
   double *hard;
   size_t n, lo, hi;
-  int status, maxp;
+  int status, maxp, mode;
 } job_t;
 
 static void *job_run(void *arg) {
   job_t *j = (job_t *)arg;
   t_maxp = 0;
+  t_mode = j->mode;
   int f = j->func, st = 0;
   for (size_t i = j->lo; i < j->hi; i++) {
     if (f == F_SINCOSF) {
@@ -1299,8 +1401,10 @@ static void *job_run(void *arg) {
 
 static int g_last_maxp = 0;
 
-static int run_jobs(int func, const void *in, void *out, double *hard, size_t n, int nthreads) {
+static int run_jobs(int func, const void *in, void *out, double *hard, size_t n, int nthreads,
+                    int mode) {
   if (kind_of(func) == -2) return -1;
+  if (mode < RM_RN || mode > RM_RD) return -3;
   if (n == 0) return 0;
   if (!in || (!out && !hard)) return -2;
   if (nthreads < 1) nthreads = 1;
@@ -1309,7 +1413,8 @@ static int run_jobs(int func, const void *in, void *out, double *hard, size_t n,
   job_t jobs[256];
   pthread_t th[256];
   for (int t = 0; t < nthreads; t++) {
-    jobs[t] = (job_t){func, in, out, hard, n, n * t / nthreads, n * (t + 1) / nthreads, 0, 0};
+    jobs[t] = (job_t){func, in, out, hard, n, n * t / nthreads, n * (t + 1) / nthreads, 0, 0,
+                      mode};
   }
   for (int t = 1; t < nthreads; t++) pthread_create(&th[t], NULL, job_run, &jobs[t]);
   job_run(&jobs[0]);
@@ -1324,11 +1429,16 @@ static int run_jobs(int func, const void *in, void *out, double *hard, size_t n,
 }
 
 int cr_oracle_eval(int func_id, const void *in, void *out, size_t n, int nthreads) {
-  return run_jobs(func_id, in, out, NULL, n, nthreads);
+  return run_jobs(func_id, in, out, NULL, n, nthreads, RM_RN);
+}
+
+int cr_oracle_eval_mode(int func_id, int mode, const void *in, void *out, size_t n,
+                        int nthreads) {
+  return run_jobs(func_id, in, out, NULL, n, nthreads, mode);
 }
 
 int cr_oracle_hardness(int func_id, const void *in, double *h, size_t n, int nthreads) {
-  return run_jobs(func_id, in, NULL, h, n, nthreads);
+  return run_jobs(func_id, in, NULL, h, n, nthreads, RM_RN);
 }
 
 int cr_oracle_last_max_prec(void) { return g_last_maxp; }

@@ -47,6 +47,14 @@ int cr_oracle_eval(int func_id, const void *in, void *out, size_t n, int nthread
  * NaN results report 0.  For sincosf the larger of the two is reported. */
 int cr_oracle_hardness(int func_id, const void *in, double *h, size_t n, int nthreads);
 
+/* As cr_oracle_eval in a given IEEE 754 rounding mode (Sec. 4.3): 0 = to
+ * nearest, ties to even (the same results as cr_oracle_eval), 1 = toward
+ * zero, 2 = toward +infinity, 3 = toward -infinity.  Overflow gives infinity
+ * or the largest finite number as the mode says; values that round to zero
+ * keep their sign.  Returns -3 for an unknown mode. */
+int cr_oracle_eval_mode(int func_id, int mode, const void *in, void *out, size_t n,
+                        int nthreads);
+
 /* Exhaustive hard-case scan of binary32 encodings [lo, hi): a cheap double
  * precision estimate (libm) selects candidates whose estimate lies within
  * 2^-h_prefilter ulp of a midpoint; each candidate is then measured with

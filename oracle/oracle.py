@@ -4,8 +4,10 @@ TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
 CPU-baseline leg of the benchmark.  The GPU library never imports it.
 
 The oracle returns RN_even(f(x)) for binary32 functions (ids 0..18) and
-binary64 exp/log/exp2 (ids 64, 65, 66), computed by a Ziv loop over a from-scratch
-fixed-point ball arithmetic (see cr_oracle.c for the method and citations).
+binary64 exp/log/exp2 (ids 64, 65, 66), or f(x) rounded in a directed mode
+(toward zero, +infinity or -infinity), computed by a Ziv loop over a
+from-scratch fixed-point ball arithmetic (see cr_oracle.c for the method and
+citations).
 """
 import ctypes
 import os
@@ -51,6 +53,8 @@ def lib():
                                      ctypes.c_size_t, ctypes.c_int]
         L.cr_oracle_hardness.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_size_t, ctypes.c_int]
+        L.cr_oracle_eval_mode.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
         L.cr_oracle_scan_f32.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_int]
@@ -79,17 +83,27 @@ def in_dtype(func):
     return np.float64 if _fid(func) >= 64 else np.float32
 
 
-def evaluate(func, x, nthreads=None):
-    """Correctly rounded f(x) for a numpy array x (float32 or float64).
-    sincosf returns an array of shape (2, n): (sin, cos)."""
+# IEEE 754 rounding modes (Sec. 4.3) of evaluate(): to nearest (ties to
+# even), toward zero, toward +infinity, toward -infinity
+MODES = {"rn": 0, "rz": 1, "ru": 2, "rd": 3}
+
+
+def evaluate(func, x, nthreads=None, mode="rn"):
+    """Correctly rounded f(x) for a numpy array x (float32 or float64), in the
+    rounding mode `mode` (a key of MODES).  sincosf returns an array of shape
+    (2, n): (sin, cos)."""
     fid = _fid(func)
     x = np.ascontiguousarray(x, dtype=in_dtype(fid))
     n = x.size
     out = np.empty(2 * n if fid == FUNC_ID["sincosf"] else n, dtype=x.dtype)
-    st = lib().cr_oracle_eval(fid, x.ctypes.data, out.ctypes.data, n,
-                              nthreads or default_threads())
+    if mode == "rn":
+        st = lib().cr_oracle_eval(fid, x.ctypes.data, out.ctypes.data, n,
+                                  nthreads or default_threads())
+    else:
+        st = lib().cr_oracle_eval_mode(fid, MODES[mode], x.ctypes.data, out.ctypes.data, n,
+                                       nthreads or default_threads())
     if st != 0:
-        raise RuntimeError("cr_oracle_eval(%s) returned %d" % (func, st))
+        raise RuntimeError("cr_oracle_eval(%s, %s) returned %d" % (func, mode, st))
     return out.reshape(2, n) if fid == FUNC_ID["sincosf"] else out
 
 
