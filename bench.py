@@ -146,6 +146,61 @@ def bench_vs_ulp(torch, crmath, inputs, n, steps, warmup, stream):
     return out
 
 
+def bench_log_tables(torch, crmath, inputs, n, steps, warmup, stream):
+    """binary64 log, the 16-entry build against the paper's 128-entry
+    scaled-integer table (Sec. II-B), on the log workload and on the paper's
+    range [0.125, 8] (Tables II, IV); the platform's ~1-ulp log on the same
+    inputs for the paper's ratio."""
+    import ctypes
+    sp = crmath._stream_ptr(stream)
+    st = inputs.Stream(4100)
+    sets = {"workload": inputs.workload_f64("log", n),
+            "uniform_0.125_8": (0.125 + 7.875 * st.uniform(n)).astype(np.float64)}
+    ref = None
+    path = os.path.join(ROOT, "paper_2605_15547_amd", "libcr_ulpref.so")
+    if os.path.exists(path):
+        ref = ctypes.CDLL(path)
+        ref.cr_ref_eval.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_size_t, ctypes.c_void_p]
+    out = {}
+    for name, x in sets.items():
+        xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+        ot = torch.empty_like(xt)
+        runs = {"t16": lambda: crmath.eval_ptr("log", xt.data_ptr(), ot.data_ptr(), n, 1, 0, sp),
+                "t128": lambda: crmath.eval_ptr("log", xt.data_ptr(), ot.data_ptr(), n,
+                                                crmath.IMPL_LOG128, 0, sp)}
+        if ref is not None:
+            runs["ulp"] = lambda: ref.cr_ref_eval(65, xt.data_ptr(), ot.data_ptr(), n, sp)
+        settle(lambda: [fn() for fn in runs.values()], 0.3, torch)
+        r = {}
+        for k, fn in runs.items():
+            for _ in range(warmup):
+                fn()
+            torch.cuda.synchronize()
+            crmath.stats_reset()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            s_ = crmath.stats_read()
+            ms = e0.elapsed_time(e1) / steps
+            r[k] = {"ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                    "hbm_frac": round(16 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            if k != "ulp":
+                r[k]["fallback_lane_rate"] = s_["fallback_lanes"] / (n * steps)
+        if "ulp" in r:
+            for k in ("t16", "t128"):
+                r[k]["ratio_vs_ulp"] = round(r[k]["gelem_s"] / r["ulp"]["gelem_s"], 3)
+        out[name] = r
+        del xt, ot
+    torch.cuda.empty_cache()
+    log("bench: log tables", out)
+    return {"elems": n, "t16": "16-entry reciprocal table, triple-double -ln c_j",
+            "t128": "128-entry scaled-integer table (CR_IMPL_LOG128)", "per_input_set": out}
+
+
 def bench_complex(torch, crmath, inputs, n, steps, warmup, stream):
     """The paper's complex expf/logf/sinf application (Sec. III-A): n complex
     numbers per function, parts uniform in [-40, 40]; 16 bytes per element."""
@@ -501,6 +556,8 @@ def main():
         if "binary64" in legs:
             extra["binary64_exp_log"] = bench_family(
                 torch, crmath, inputs, list(F64), 1 << 24, 0, a.steps, a.warmup, stream)
+            extra["binary64_log_tables"] = bench_log_tables(torch, crmath, inputs, 1 << 24,
+                                                            a.steps, a.warmup, stream)
         if "vsulp" in legs:
             extra["vs_ulp_library"] = bench_vs_ulp(torch, crmath, inputs, n, a.steps, a.warmup,
                                                    stream)

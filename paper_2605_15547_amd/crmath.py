@@ -24,7 +24,7 @@ FUNC_ID["clogf"] = 81
 FUNC_ID["csinf"] = 82
 COMPLEX = ["cexpf", "clogf", "csinf"]
 
-IMPL_AUTO, IMPL_F64_INTERNAL, IMPL_SPLIT_F32 = 0, 1, 2
+IMPL_AUTO, IMPL_F64_INTERNAL, IMPL_SPLIT_F32, IMPL_LOG128 = 0, 1, 2, 3
 FLAG_FORCE_FALLBACK = 1
 
 CR_OK = 0

@@ -469,4 +469,76 @@ __device__ __noinline__ AccResultD log64_accurate(double x, const Log64Tab& tb) 
   return {res, ok ? 1 : 0};
 }
 
+// ------------------------------------------------- log, 128-entry table
+// The paper's cr_log main path (Sec. II-B): a short reciprocal rcp of the
+// mantissa m in [0.75, 1.5) and ONE 64-bit table read per element, a scaled
+// integer that becomes a double-double.  Here rcp is the hardware binary32
+// reciprocal of m rounded to 8 significant bits, so it takes the 128 binary32
+// values with encodings (0x3F2B + j) << 16, j = 0..127 (0.66796875 ..
+// 1.328125; the one value above, reached from m just above 0.75 only, is
+// clamped to j = 127), and |t| = |m rcp - 1| <= 2^-8 (1 + 2^-12).  With
+// r = rcp - 1 (exact) the entry holds T = log1p(r)/r - 1 as the integer
+// nearest to T 2^65, so -ln rcp = -(r + r T) and
+//   ln x = e' ln2 - (r + r Th) - r Tl + log1p(t),
+// T = Th + Tl from the integer's two 32-bit halves; r + r Th and r Tl are
+// exact (8 x 32-bit products on the 2^-41 and 2^-73 grids).  log1p t =
+// t - t^2/2 + t^3/3 + t^4 S(t) with S of low degree (|t| <= 2^-8).
+// The accurate path is the 16-entry one above (log64_accurate).
+struct Log128Tab {
+  long long T[128];
+  Log64Tab acc;
+};
+
+__device__ __forceinline__ void log128_tab_load(Log128Tab& t, int tid) {
+  if (tid < 128) t.T[tid] = LOG128_T[tid];
+  log64_tab_load(t.acc, tid);
+}
+
+// Main-path error, relative to y (|y| >= 0.28 when e' != 0; when e' = 0,
+// |y| >= |r|/2 (1 - 2^-12): m then lies in the rounding interval of rcp, at
+// least half a spacing of 8-bit values away from 1/1 = 1, and |y| >= 0.99 |t|
+// when r = 0):
+//  * the table: T to 2^-66, so -ln rcp within |r| 2^-66 <= 2^-64.97 |y|;
+//  * t^3/3 in binary64 (t2.hi t.hi THIRD: about 3.5 units of 2^-53 of
+//    |t|^3/3 <= 2^-68.8 |t|) and t^4 S (below 2^-75 |t|), |t| <= 2 |y| when
+//    r != 0: within 2^-67.8 |y|;
+//  * t^2/2 and the sums in double-double, e' ln2 to 2^-106: below 2^-98 |y|.
+// In all below 2^-64.6 |y|; the test allows 2^-64 |y|.
+constexpr double LOG128_EPS = 0x1p-64;
+
+__device__ __forceinline__ double log128_fast(double x, const Log128Tab& tb, bool& ok) {
+  Log64Setup S = log64_setup(x);
+  const float ra = __builtin_amdgcn_rcpf((float)S.m);
+  int j = (int)((f32_bits(ra) + 0x8000u) >> 16) - 0x3F2B;
+  j = j > 127 ? 127 : (j < 0 ? 0 : j);
+  const double rcp = (double)bits_f32((uint32_t)(0x3F2B + j) << 16);
+  const long long Ti = tb.T[j];
+  const double Th = (double)(int)(Ti >> 32) * 0x1p-33;
+  const double Tl = (double)(uint32_t)Ti * 0x1p-65;
+  const double r = rcp - 1.0;
+  dd A = fast_two_sum(-(r + r * Th), -(r * Tl));  // -ln rcp
+  dd p = two_prod(S.m, rcp);
+  dd t = fast_two_sum(p.hi - 1.0, p.lo);  // exact: p.hi in [1 - 2^-7, 1 + 2^-7]
+  dd t2 = two_prod(t.hi, t.hi);
+  t2.lo = fma(2.0 * t.hi, t.lo, t2.lo);
+  double sp = LOG128_S[LOG128_S_DEG];
+#pragma unroll
+  for (int i = LOG128_S_DEG - 1; i >= 0; i--) sp = fma(sp, t.hi, LOG128_S[i]);
+  const double b3 = (t2.hi * t.hi) * THIRD_HI + t2.hi * t2.hi * sp;
+  dd l = dd_add_ord(t, dd{-0.5 * t2.hi, -0.5 * t2.lo});
+  l = fast_two_sum(l.hi, l.lo + b3);
+  dd el = dd_mul_d(dd{LN2_TD[0].x, LN2_TD[0].y}, (double)S.e2);
+  dd y = dd_add_nc(dd_add_nc(el, A), l);
+  double e = fabs(y.hi) * LOG128_EPS;
+  double a = y.hi + (y.lo - e);
+  double b = y.hi + (y.lo + e);
+  ok = a == b;
+  double res = b, spv;
+  if (log64_special(x, spv)) {
+    res = spv;
+    ok = true;
+  }
+  return res;
+}
+
 }  // namespace cr

@@ -646,6 +646,19 @@ struct OpLog64 {
   }
 };
 
+// binary64 log with the paper's 128-entry scaled-integer table (main path);
+// lanes that fail its test take the 16-entry accurate path
+struct OpLog128 {
+  using Tab = Log128Tab;
+  static constexpr int qcheck = QCHECK;
+  static __device__ __forceinline__ void load(Tab& t, int tid) { log128_tab_load(t, tid); }
+  static __device__ __forceinline__ double fast(double x, const Tab& t, bool& ok) {
+    return log128_fast(x, t, ok);
+  }
+  static __device__ __forceinline__ AccResultD accurate(double x, const Tab& t) {
+    return log64_accurate(x, t.acc);
+  }
+};
 struct OpExp2_64 {
   using Tab = Exp2_64Tab;
   static constexpr int qcheck = QCHECK;
@@ -1552,6 +1565,10 @@ int launch_complex(const float* in, float* out, size_t n, hipStream_t s, unsigne
 }
 
 bool func_complex(int f) { return f == CR_CEXPF || f == CR_CLOGF || f == CR_CSINF; }
+bool impl_valid(int impl) {
+  return impl == CR_IMPL_AUTO || impl == CR_IMPL_F64_INTERNAL || impl == CR_IMPL_SPLIT_F32 ||
+         impl == CR_IMPL_LOG128;
+}
 bool func_f64(int f) { return f == CR_EXP || f == CR_LOG || f == CR_EXP2; }
 bool func_valid(int f) { return (f >= 0 && f < CR_NUM_F32) || func_f64(f) || func_complex(f); }
 bool func_built(int f) {
@@ -1649,6 +1666,8 @@ int eval_cfg(int func_id, int impl, unsigned flags, const void* in, void* out, s
     rc = launch_map_f64<OpExp64>((const double*)in, (double*)out, n, s, flags, st, g);
   else if (func_id == CR_EXP2)
     rc = launch_map_f64<OpExp2_64>((const double*)in, (double*)out, n, s, flags, st, g);
+  else if (func_id == CR_LOG && impl == CR_IMPL_LOG128)
+    rc = launch_map_f64<OpLog128>((const double*)in, (double*)out, n, s, flags, st, g);
   else if (func_id == CR_CEXPF)
     rc = launch_complex<CExpF>((const float*)in, (float*)out, n, s, flags, st, g);
   else if (func_id == CR_CLOGF)
@@ -1846,8 +1865,7 @@ int cr_available(int func_id, int impl);
 int cr_eval_ex(int func_id, int impl, unsigned flags, const void* in, void* out, size_t n,
                void* stream) {
   if (!func_valid(func_id)) return CR_E_FUNC;
-  if (impl != CR_IMPL_AUTO && impl != CR_IMPL_F64_INTERNAL && impl != CR_IMPL_SPLIT_F32)
-    return CR_E_IMPL;
+  if (!impl_valid(impl)) return CR_E_IMPL;
   if (n == 0) return CR_OK;
   if (!in || !out) return CR_E_NULL;
   const size_t es = elem_bytes(func_id), al = func_complex(func_id) ? 4 : es;
@@ -1876,8 +1894,7 @@ int cr_tune_variant_info(int variant, int* elems_per_thread, int* prefetch, int*
 
 static int tune_check(int func_id, int impl, const cr_tune_cfg* cfg) {
   if (!func_valid(func_id)) return CR_E_FUNC;
-  if (impl != CR_IMPL_AUTO && impl != CR_IMPL_F64_INTERNAL && impl != CR_IMPL_SPLIT_F32)
-    return CR_E_IMPL;
+  if (!impl_valid(impl)) return CR_E_IMPL;
   if (!cfg) return CR_E_NULL;
   if (cfg->variant < 0 || cfg->variant >= num_variants_of(func_id)) return CR_E_TUNE;
   if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64) return CR_E_TUNE;
@@ -1886,8 +1903,7 @@ static int tune_check(int func_id, int impl, const cr_tune_cfg* cfg) {
 
 int cr_tune_get(int func_id, int impl, cr_tune_cfg* cfg) {
   if (!func_valid(func_id)) return CR_E_FUNC;
-  if (impl != CR_IMPL_AUTO && impl != CR_IMPL_F64_INTERNAL && impl != CR_IMPL_SPLIT_F32)
-    return CR_E_IMPL;
+  if (!impl_valid(impl)) return CR_E_IMPL;
   if (!cfg) return CR_E_NULL;
   const int ii = iidx(impl), fi = fidx(func_id);
   cfg->variant = g_cfg_variant[ii][fi].load();
@@ -1972,8 +1988,7 @@ int cr_tune_load(const char* path) {
 int cr_autotune(int func_id, int impl, const void* in, void* out, size_t n, int reps,
                 void* stream, double* best_gelem_s) {
   if (!func_valid(func_id)) return CR_E_FUNC;
-  if (impl != CR_IMPL_AUTO && impl != CR_IMPL_F64_INTERNAL && impl != CR_IMPL_SPLIT_F32)
-    return CR_E_IMPL;
+  if (!impl_valid(impl)) return CR_E_IMPL;
   if (n == 0 || !in || !out) return CR_E_NULL;
   const size_t es = elem_bytes(func_id), al = func_complex(func_id) ? 4 : es;
   const size_t nout = func_id == CR_SINCOSF ? 2 * n : n;
@@ -2056,6 +2071,7 @@ int cr_autotune(int func_id, int impl, const void* in, void* out, size_t n, int 
 int cr_available(int func_id, int impl) {
   if (!func_valid(func_id)) return 0;
   if (impl == CR_IMPL_SPLIT_F32) return split_built(func_id) ? 1 : 0;
+  if (impl == CR_IMPL_LOG128) return func_id == CR_LOG ? 1 : 0;
   if (impl != CR_IMPL_AUTO && impl != CR_IMPL_F64_INTERNAL) return 0;
   return func_built(func_id) ? 1 : 0;
 }

@@ -473,6 +473,47 @@ def gen_f64():
     emit_dd_table("INV_ODD_DD", [mp.mpf(1) / (2 * k + 1) for k in range(17)], "1/(2k+1), k = 0..16")
     emit()
     gen_exp2_64()
+    gen_log128()
+
+
+def gen_log128():
+    """binary64 log with the paper's 128-entry scaled-integer table (Sec. II-B):
+    rcp_j = the binary32 value with encoding (0x3F2B + j) << 16 (8 significant
+    bits, 0.66796875 .. 1.328125), r_j = rcp_j - 1 (exact) and the entry
+    T_j = log1p(r_j)/r_j - 1 stored as the 64-bit integer nearest to T_j 2^65."""
+    emit("// ---- binary64 log, 128-entry scaled-integer table ----")
+    vals = []
+    with mp.workprec(400):
+        for j in range(128):
+            enc = (0x3F2B + j) << 16
+            sign, ex, man = enc >> 31, (enc >> 23) & 0xFF, enc & 0x7FFFFF
+            rcp = (1 + mp.mpf(man) / 2 ** 23) * mp.mpf(2) ** (ex - 127)
+            r = rcp - 1
+            T = mp.mpf(0) if r == 0 else mp.log1p(r) / r - 1
+            vals.append(int(mp.nint(T * mp.mpf(2) ** 65)))
+    assert all(abs(v) < 2 ** 63 for v in vals)
+    emit("// T_j = log1p(r_j)/r_j - 1 scaled by 2^65 (r_j = rcp_j - 1, rcp_j = binary32 with "
+         "encoding (0x3F2B + j) << 16)")
+    emit("__device__ __constant__ const long long LOG128_T[128] = {")
+    for i in range(0, 128, 4):
+        emit("  " + " ".join("%dll," % v for v in vals[i:i + 4]))
+    emit("};")
+    # log1p t = t - t^2/2 + t^3/3 + t^4 S(t), |t| <= 2^-8 (1 + 2^-12)
+    rho = mp.mpf(2) ** -8 * (1 + mp.mpf(2) ** -12)
+    g = lambda t: (mp.log1p(t) - t + t * t / 2 - t ** 3 / 3) / t ** 4 if t != 0 else mp.mpf(-1) / 4
+    for deg in range(1, 8):
+        cs = lawson_fit(g, lambda t: t ** 4, -rho, rho, list(range(deg + 1)), npts=100, iters=12)
+        cd = [d(v) for v in cs]
+        err = max_err(lambda t: mp.log1p(t) - t + t * t / 2 - t ** 3 / 3
+                      - t ** 4 * sum(mp.mpf(cd[k]) * t ** k for k in range(len(cd))), -rho, rho)
+        if err < mp.mpf(2) ** -88:
+            break
+    Sm = [mp.mpf(v) for v in cd]
+    emit("// log1p t = t - t^2/2 + t^3/3 + t^4 S(t), |t| <= 2^-8 (1 + 2^-12); |error| <= 2^%.2f "
+         "(absolute, proven)" % log2_of(B.sup_bound(B.log64_absolute(Sm, -rho, rho))))
+    emit_arr("LOG128_S", cd, "coefficients (degree %d)" % (len(cd) - 1))
+    emit("#define LOG128_S_DEG %d" % (len(cd) - 1))
+    emit()
 
 
 def gen_exp2_64():

@@ -124,3 +124,41 @@ def test_bound_method_is_tight_and_sound():
     exact = mp.exp(rho) - 1 - rho - rho ** 2 / 2 - rho ** 3 / 6
     got = B.sup_bound(B.expm1_minus_r([mp.mpf(1) / 2, mp.mpf(1) / 6], rho), pieces=128)
     assert exact <= got <= exact * mp.mpf("1.02"), (exact, got)
+
+
+def test_exp2_64_main_path_polynomial(hdr):
+    """binary64 exp2 main path (cr_f64.h): r = R ln2 with |R| <= 2^-13 (exact),
+    so |r| <= ln2/8192; the budget takes P's approximation error as 2^-91.95
+    of an error total of 2^-78.5 (the rounding test allows 2^-77)."""
+    rho = mp.log(2) / 8192 * (1 + mp.mpf(2) ** -40)
+    b = proven(B.expm1_minus_r(arr(hdr, "EXP2_64_P"), rho))
+    assert b <= -91.9, b
+    assert b <= printed_bound(hdr, "|r| <= ln2/8192") + 0.01, b
+
+
+def test_log128_main_path_polynomial(hdr):
+    """binary64 log with the 128-entry table (cr_f64.h): |t| <= 2^-8 (1 + 2^-12);
+    the budget takes t^4 S as within 2^-75 |t| (2^-83 absolute at the ends)."""
+    rho = mp.mpf(2) ** -8 * (1 + mp.mpf(2) ** -12)
+    S = arr(hdr, "LOG128_S")
+    ab = proven(B.log64_absolute(S, -rho, rho))
+    assert ab <= -83, ab
+    assert ab <= printed_bound(hdr, "|t| <= 2^-8 (1 + 2^-12)") + 0.01, ab
+
+
+def test_log128_table_entries(hdr):
+    """The 128 scaled integers are log1p(r)/r - 1 for the reciprocals of 8
+    significant bits, to within half a unit of 2^-65."""
+    m = re.search(r"LOG128_T\[128\] = \{([^}]*)\}", hdr)
+    vals = [int(v.strip().rstrip("l")) for v in m.group(1).replace("ll", "").split(",")
+            if v.strip()]
+    assert len(vals) == 128
+    with mp.workprec(200):
+        for j, v in enumerate(vals):
+            enc = (0x3F2B + j) << 16
+            rcp = (1 + mp.mpf(enc & 0x7FFFFF) / 2 ** 23) * mp.mpf(2) ** (((enc >> 23) & 0xFF) - 127)
+            r = rcp - 1
+            T = mp.mpf(0) if r == 0 else mp.log1p(r) / r - 1
+            assert abs(T * mp.mpf(2) ** 65 - v) <= 0.5, j
+    # rcp = 1 (j = 85) has T = 0
+    assert abs(vals[85]) == 0  # rcp = 1

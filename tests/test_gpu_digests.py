@@ -124,11 +124,11 @@ def test_trig_family_2p26_digest(func, impl):
     _check_array("trig_2p26." + func, func, inputs.workload_f32(func, 1 << 26), impl[1])
 
 
-@pytest.mark.parametrize("func", F64)
-def test_binary64_2p24_digest(func):
+@pytest.mark.parametrize("func,impl", [(f, crmath.IMPL_AUTO) for f in F64]
+                         + [("log", crmath.IMPL_LOG128)], ids=list(F64) + ["log-t128"])
+def test_binary64_2p24_digest(func, impl):
     _need_gpu()
-    _check_array("binary64_2p24." + func, func, inputs.workload_f64(func, 1 << 24),
-                 crmath.IMPL_AUTO)
+    _check_array("binary64_2p24." + func, func, inputs.workload_f64(func, 1 << 24), impl)
 
 
 @pytest.fixture(scope="module")

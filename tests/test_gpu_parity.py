@@ -265,3 +265,36 @@ def test_function_edges(oracle, func, impl):
     assert_same(func, x, gpu_eval(func, x, impl=impl), ref)
     assert_same(func, x, gpu_eval(func, x, impl=impl, flags=crmath.FLAG_FORCE_FALLBACK), ref)
     assert crmath.stats_read()["escapes"] == 0
+
+
+def test_log_128_entry_table_variant(oracle):
+    """binary64 log through the paper's 128-entry scaled-integer table
+    (CR_IMPL_LOG128): ragged sizes, the hard set, specials and edges, the
+    paper's range [0.125, 8] and the accurate path forced, against the oracle;
+    and on 2^24 inputs every certified main-path result equals the forced
+    accurate path's."""
+    _need_gpu()
+    impl = crmath.IMPL_LOG128
+    assert crmath.available("log", impl) and not crmath.available("exp", impl)
+    st = inputs.Stream(4242)
+    cases = [workload("log", n, seed=20_000 + n) for n in (1, 3, 2047, 2049, 70001)]
+    cases.append(inputs.hard_set("log"))
+    cases.append(_edge_inputs("log"))
+    cases.append(np.array([0.0, -0.0, np.inf, -np.inf, 1.0, -1.0, 5e-324, 2.0 ** -1022,
+                           1.7976931348623157e308, 0.75, np.nextafter(0.75, 0), 1.5,
+                           np.nextafter(1.5, 0), 1 + 2.0 ** -52, 1 - 2.0 ** -53], np.float64))
+    cases.append((0.125 * 64.0 ** st.uniform(1 << 16)).astype(np.float64))  # log-uniform [1/8, 8]
+    cases.append((0.125 + 7.875 * st.uniform(1 << 16)).astype(np.float64))  # uniform [1/8, 8]
+    crmath.stats_reset()
+    for x in cases:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        ref = oracle.evaluate("log", x)
+        assert_same("log", x, gpu_eval("log", x, impl=impl), ref)
+        assert_same("log", x, gpu_eval("log", x, impl=impl, flags=crmath.FLAG_FORCE_FALLBACK), ref)
+    assert crmath.stats_read()["escapes"] == 0
+    for x in (workload("log", 1 << 24, seed=79),
+              (0.125 + 7.875 * st.uniform(1 << 24)).astype(np.float64)):
+        a = gpu_eval("log", x, impl=impl)
+        b = gpu_eval("log", x, impl=impl, flags=crmath.FLAG_FORCE_FALLBACK)
+        bad = np.nonzero(bits(a) != bits(b))[0]
+        assert bad.size == 0, (bad.size, hex(int(bits(x)[bad[0]])))
