@@ -94,8 +94,24 @@ enum cr_impl {
 enum cr_flag {
   /* every element also takes the accurate path (testing aid); results are
    * identical by construction, only slower */
-  CR_FLAG_FORCE_FALLBACK = 1u
+  CR_FLAG_FORCE_FALLBACK = 1u,
+  /* Rounding mode of the results (IEEE 754-2019 Sec. 4.3; the paper's CPU
+   * library supports every mode, Sec. II-A, its GPU runs were round to
+   * nearest only, Sec. III-C).  Default (none of these): to nearest, ties to
+   * even.  Toward zero / +infinity / -infinity are available for the binary32
+   * functions (ids 0..18) with CR_IMPL_AUTO or CR_IMPL_F64_INTERNAL through
+   * cr_eval_ex; other functions and implementations, and batch plans, return
+   * CR_E_IMPL.  Overflow gives +-infinity or +-FLT_MAX as the mode
+   * says (Sec. 7.4); results that round to zero keep their sign.  Each
+   * element takes a double-double evaluation (about 2^-100 relative) with
+   * both ends of its error interval rounded in the mode, so these modes run
+   * at the accurate path's speed. */
+  CR_FLAG_ROUND_TOWARD_ZERO = 1u << 4,
+  CR_FLAG_ROUND_UP = 2u << 4,
+  CR_FLAG_ROUND_DOWN = 3u << 4
 };
+#define CR_FLAG_ROUND_SHIFT 4
+#define CR_FLAG_ROUND_MASK (3u << CR_FLAG_ROUND_SHIFT)
 
 enum cr_status {
   CR_OK = 0,

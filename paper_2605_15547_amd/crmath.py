@@ -26,6 +26,10 @@ COMPLEX = ["cexpf", "clogf", "csinf"]
 
 IMPL_AUTO, IMPL_F64_INTERNAL, IMPL_SPLIT_F32, IMPL_LOG128 = 0, 1, 2, 3
 FLAG_FORCE_FALLBACK = 1
+# rounding modes (enum cr_flag): to nearest is the default
+FLAG_ROUND_TOWARD_ZERO, FLAG_ROUND_UP, FLAG_ROUND_DOWN = 1 << 4, 2 << 4, 3 << 4
+ROUND_FLAGS = {"rn": 0, "rz": FLAG_ROUND_TOWARD_ZERO, "ru": FLAG_ROUND_UP,
+               "rd": FLAG_ROUND_DOWN}
 
 CR_OK = 0
 STATUS = {0: "CR_OK", -1: "CR_E_FUNC", -2: "CR_E_NULL", -3: "CR_E_OVERLAP", -4: "CR_E_ALIGN",

@@ -25,6 +25,7 @@
 #include "cr_f32_atan.h"
 #include "cr_f32_hyp.h"
 #include "cr_f64.h"
+#include "cr_f32_dir.h"
 #include "cr_split_exp.h"
 #include "cr_split_log.h"
 #include "cr_split_trig.h"
@@ -106,6 +107,7 @@ __device__ __forceinline__ void st_stream(double2* p, double2 a) {
 // ------------------------------------------------------------ evaluators
 // Op::fast(x, tab, ok): binary64 fast path and rounding test (inlined).
 // Op::accurate(x, tab): double-double path from x alone (out of line).
+// Op::dir<RM>(x, tab): the result in a directed rounding mode (out of line).
 template <int K>
 struct OpExp {
   using Tab = ExpTab;
@@ -116,6 +118,10 @@ struct OpExp {
   }
   static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
     return exp_accurate<K>(x, t);
+  }
+  template <int RM>
+  static __device__ __forceinline__ AccResult dir(float x, const Tab& t) {
+    return exp_dir<K, RM>(x, t);
   }
 };
 
@@ -129,6 +135,10 @@ struct SinCosF64 {
   }
   static __device__ __forceinline__ AccResult2 accurate(float x, const Tab& t) {
     return sincos_accurate(x, t);
+  }
+  template <int RM>
+  static __device__ __forceinline__ AccResult2 dir(float x, const Tab& t) {
+    return sincos_dir<RM>(x, t);
   }
 };
 struct SinCosSplit {
@@ -234,6 +244,10 @@ struct OpLog {
   static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
     return log_accurate<K>(x, t);
   }
+  template <int RM>
+  static __device__ __forceinline__ AccResult dir(float x, const Tab& t) {
+    return log_dir<K, RM>(x, t);
+  }
 };
 
 // rsqrtf decides its rounding exactly in the fast path: nothing is deferred.
@@ -248,6 +262,10 @@ struct OpRsqrt {
     bool ok;
     return {rsqrt_fast(x, ok), 1};
   }
+  template <int RM>
+  static __device__ __forceinline__ AccResult dir(float x, const Tab&) {
+    return rsqrt_dir<RM>(x);
+  }
 };
 
 template <int KIND>
@@ -260,6 +278,10 @@ struct OpTrig {
   }
   static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
     return trig_accurate<KIND>(x, t);
+  }
+  template <int RM>
+  static __device__ __forceinline__ AccResult dir(float x, const Tab& t) {
+    return trig_dir<KIND, RM>(x, t);
   }
 };
 
@@ -274,6 +296,10 @@ struct OpAtan {
   static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
     return atan_accurate<KIND>(x, t);
   }
+  template <int RM>
+  static __device__ __forceinline__ AccResult dir(float x, const Tab& t) {
+    return atan_dir<KIND, RM>(x, t);
+  }
 };
 
 template <int KIND>
@@ -286,6 +312,10 @@ struct OpHyp {
   }
   static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
     return hyp_accurate<KIND>(x, t);
+  }
+  template <int RM>
+  static __device__ __forceinline__ AccResult dir(float x, const Tab& t) {
+    return hyp_dir<KIND, RM>(x, t);
   }
 };
 
@@ -777,6 +807,55 @@ __global__ void __launch_bounds__(BLOCK)
       if (!a.ok) note_escape(st, elem_base + i);
     }
     out[i] = r;
+  }
+  if (lanes) {
+    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
+    atomicAdd(&c.fallback_lanes, (unsigned long long)lanes);
+    atomicAdd(&c.fallback_waves, 1ull);
+  }
+}
+
+// ------------------------------------------------- directed rounding modes
+// Every element through the function's ~2^-100 double-double evaluation with
+// both ends of its error interval rounded in the mode RM (cr_f32_dir.h); the
+// paper's GPU runs leave these modes out (Sec. III-C).  A grid-stride map with
+// the tables in LDS; each element counts as an accurate-path lane.
+template <class Op, int RM>
+__global__ void __launch_bounds__(BLOCK)
+    k_map_f32_dir(const float* in, float* out, long long n, DevStats* st, long long elem_base) {
+  __shared__ typename Op::Tab tab;
+  Op::load(tab, threadIdx.x);
+  __syncthreads();
+  unsigned lanes = 0;
+  for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n;
+       i += (long long)gridDim.x * BLOCK) {
+    AccResult a = Op::template dir<RM>(in[i], tab);
+    out[i] = a.r;
+    lanes++;
+    if (!a.ok) note_escape(st, elem_base + i);
+  }
+  if (lanes) {
+    CounterSlot& c = st->slot[blockIdx.x % NSLOT];
+    atomicAdd(&c.fallback_lanes, (unsigned long long)lanes);
+    atomicAdd(&c.fallback_waves, 1ull);
+  }
+}
+
+template <class SC, int RM>
+__global__ void __launch_bounds__(BLOCK)
+    k_sincos_dir(const float* in, float* outs, float* outc, long long n, DevStats* st,
+                 long long elem_base) {
+  __shared__ typename SC::Tab tab;
+  SC::load(tab, threadIdx.x);
+  __syncthreads();
+  unsigned lanes = 0;
+  for (long long i = (long long)blockIdx.x * BLOCK + threadIdx.x; i < n;
+       i += (long long)gridDim.x * BLOCK) {
+    AccResult2 a = SC::template dir<RM>(in[i], tab);
+    outs[i] = a.s;
+    outc[i] = a.c;
+    lanes++;
+    if (!a.ok) note_escape(st, elem_base + i);
   }
   if (lanes) {
     CounterSlot& c = st->slot[blockIdx.x % NSLOT];
@@ -1632,6 +1711,61 @@ int dispatch_f32(int f, const float* in, float* out, size_t n, hipStream_t s, un
 }
 
 
+// Directed rounding modes: one grid-stride kernel per (function, mode).
+template <class Op, int RM>
+int launch_dir(const float* in, float* out, size_t n, hipStream_t s, DevStats* st, int grid) {
+  size_t g = (n + BLOCK - 1) / BLOCK;
+  if (g > (size_t)grid) g = grid;
+  hipLaunchKernelGGL((k_map_f32_dir<Op, RM>), dim3((unsigned)g), dim3(BLOCK), 0, s, in, out,
+                     (long long)n, st, 0LL);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CR_OK : hip_fail(e);
+}
+
+template <int RM>
+int dispatch_f32_dir(int f, const float* in, float* out, size_t n, hipStream_t s, DevStats* st,
+                     int g) {
+  switch (f) {
+    case CR_EXPF: return launch_dir<OpExp<EXPK_E>, RM>(in, out, n, s, st, g);
+    case CR_EXP2F: return launch_dir<OpExp<EXPK_2>, RM>(in, out, n, s, st, g);
+    case CR_EXP10F: return launch_dir<OpExp<EXPK_10>, RM>(in, out, n, s, st, g);
+    case CR_EXPM1F: return launch_dir<OpExp<EXPK_EM1>, RM>(in, out, n, s, st, g);
+    case CR_LOGF: return launch_dir<OpLog<LOGK_E>, RM>(in, out, n, s, st, g);
+    case CR_LOG2F: return launch_dir<OpLog<LOGK_2>, RM>(in, out, n, s, st, g);
+    case CR_LOG10F: return launch_dir<OpLog<LOGK_10>, RM>(in, out, n, s, st, g);
+    case CR_LOG1PF: return launch_dir<OpLog<LOGK_1P>, RM>(in, out, n, s, st, g);
+    case CR_RSQRTF: return launch_dir<OpRsqrt, RM>(in, out, n, s, st, g);
+    case CR_SINF: return launch_dir<OpTrig<TRIGK_SIN>, RM>(in, out, n, s, st, g);
+    case CR_COSF: return launch_dir<OpTrig<TRIGK_COS>, RM>(in, out, n, s, st, g);
+    case CR_TANF: return launch_dir<OpTrig<TRIGK_TAN>, RM>(in, out, n, s, st, g);
+    case CR_ASINF: return launch_dir<OpAtan<ATANK_ASIN>, RM>(in, out, n, s, st, g);
+    case CR_ACOSF: return launch_dir<OpAtan<ATANK_ACOS>, RM>(in, out, n, s, st, g);
+    case CR_ATANF: return launch_dir<OpAtan<ATANK_ATAN>, RM>(in, out, n, s, st, g);
+    case CR_SINHF: return launch_dir<OpHyp<HYPK_SINH>, RM>(in, out, n, s, st, g);
+    case CR_COSHF: return launch_dir<OpHyp<HYPK_COSH>, RM>(in, out, n, s, st, g);
+    case CR_TANHF: return launch_dir<OpHyp<HYPK_TANH>, RM>(in, out, n, s, st, g);
+    case CR_SINCOSF: {
+      size_t gg = (n + BLOCK - 1) / BLOCK;
+      if (gg > (size_t)g) gg = g;
+      hipLaunchKernelGGL((k_sincos_dir<SinCosF64, RM>), dim3((unsigned)gg), dim3(BLOCK), 0, s, in,
+                         out, out + n, (long long)n, st, 0LL);
+      hipError_t e = hipGetLastError();
+      return e == hipSuccess ? CR_OK : hip_fail(e);
+    }
+  }
+  return CR_E_FUNC;
+}
+
+int dispatch_dir(int mode, int f, const float* in, float* out, size_t n, hipStream_t s,
+                 DevStats* st, int g) {
+  switch (mode) {
+    case RM_RZ: return dispatch_f32_dir<RM_RZ>(f, in, out, n, s, st, g);
+    case RM_RU: return dispatch_f32_dir<RM_RU>(f, in, out, n, s, st, g);
+    case RM_RD: return dispatch_f32_dir<RM_RD>(f, in, out, n, s, st, g);
+  }
+  return CR_E_IMPL;
+}
+
 // ------------------------------------------------------------ tuning table
 // One launch configuration per (implementation, function): a k_map_f32
 // variant and the persistent grid in workgroups per compute unit.  Index 0 of
@@ -1658,7 +1792,10 @@ int eval_cfg(int func_id, int impl, unsigned flags, const void* in, void* out, s
   int rc = get_stats(&st);
   if (rc) return rc;
   const int g = num_cus() * (bpc > 0 ? bpc : default_bpc());
-  if (func_id < CR_NUM_F32 && impl == CR_IMPL_SPLIT_F32)
+  const int mode = (int)((flags & CR_FLAG_ROUND_MASK) >> CR_FLAG_ROUND_SHIFT);
+  if (mode != RM_RN)
+    rc = dispatch_dir(mode, func_id, (const float*)in, (float*)out, n, s, st, g);
+  else if (func_id < CR_NUM_F32 && impl == CR_IMPL_SPLIT_F32)
     rc = dispatch_f32_split(func_id, (const float*)in, (float*)out, n, s, flags, st, variant, g);
   else if (func_id < CR_NUM_F32)
     rc = dispatch_f32(func_id, (const float*)in, (float*)out, n, s, flags, st, variant, g);
@@ -1876,6 +2013,9 @@ int cr_eval_ex(int func_id, int impl, unsigned flags, const void* in, void* out,
   bool same = a == b && nout == n;
   if (!same && a < b + nout * es && b < a + n * es) return CR_E_OVERLAP;
   if (!cr_available(func_id, impl)) return CR_E_IMPL;
+  if ((flags & CR_FLAG_ROUND_MASK) &&
+      (func_id >= CR_NUM_F32 || impl == CR_IMPL_SPLIT_F32 || impl == CR_IMPL_LOG128))
+    return CR_E_IMPL;  // directed modes: the binary32 functions, binary64-internal
   const int ii = iidx(impl), fi = fidx(func_id);
   return eval_cfg(func_id, impl, flags, in, out, n, (hipStream_t)stream,
                   g_cfg_variant[ii][fi].load(), g_cfg_bpc[ii][fi].load());
@@ -2130,6 +2270,7 @@ int cr_batch_plan_create(const cr_request* reqs, int32_t num, unsigned flags,
                          cr_batch_plan** plan) {
   if (!plan) return CR_E_NULL;
   *plan = nullptr;
+  if (flags & CR_FLAG_ROUND_MASK) return CR_E_IMPL;  // batches round to nearest
   std::vector<BReq> hr;
   std::vector<BTile> ht;
   long long elems = 0;

@@ -102,4 +102,84 @@ __device__ __forceinline__ float round_f32_dd(double h, double l, double drel, b
   return b;
 }
 
+// ---------------------------------------------------- directed rounding
+// The rounding modes of IEEE 754-2019 Sec. 4.3 that the paper's CPU library
+// offers besides round to nearest (Sec. II-A; its GPU runs were round to
+// nearest only, Sec. III-C).  Here they are reached from round-to-nearest
+// hardware: a binary64 value v is converted to binary32 to nearest, and the
+// result is moved by one ulp when it lies on the wrong side of v.
+enum { RM_RN = 0, RM_RZ = 1, RM_RU = 2, RM_RD = 3 };
+
+// The next binary32 number above / below r (r finite or an infinity reached
+// from the other side; from +-0 the smallest subnormal of that direction).
+__device__ __forceinline__ float f32_next_up(float r) {
+  const uint32_t b = f32_bits(r);
+  if ((b & 0x7fffffffu) == 0) return bits_f32(1u);
+  return bits_f32((b >> 31) ? b - 1 : b + 1);
+}
+__device__ __forceinline__ float f32_next_down(float r) {
+  const uint32_t b = f32_bits(r);
+  if ((b & 0x7fffffffu) == 0) return bits_f32(0x80000001u);
+  return bits_f32((b >> 31) ? b + 1 : b - 1);
+}
+
+// v (binary64, not NaN) rounded to binary32 in mode RM, overflow included:
+// RN(v) is exact in binary64, so comparing it with v tells on which side of
+// v it lies.
+template <int RM>
+__device__ __forceinline__ float cvt_f32_mode(double v) {
+  const float r = (float)v;
+  if (RM == RM_RN) return r;
+  const double back = (double)r;
+  const bool above = back > v, below = back < v;  // r above / below v
+  const bool toward_zero_up = v < 0.0;            // for RZ: the direction of zero
+  if (RM == RM_RU) return below ? f32_next_up(r) : r;
+  if (RM == RM_RD) return above ? f32_next_down(r) : r;
+  // RZ
+  if (toward_zero_up) return below ? f32_next_up(r) : r;
+  return above ? f32_next_down(r) : r;
+}
+
+// Accurate-path rounding in mode RM of h + l (|l| <= ulp(h)/2) known to within
+// a relative error drel: both ends as round-to-odd binary64 numbers, then the
+// mode's conversion.  A binary32 number is an even binary64 number, so a
+// round-to-odd value lies strictly between the same two binary32 numbers as
+// the exact one, and any rounding of it to binary32 is the rounding of the
+// exact value (Boldo and Melquiond, cited above).
+template <int RM>
+__device__ __forceinline__ float round_f32_dd_mode(double h, double l, double drel, bool& ok) {
+  double e = fabs(h) * drel;
+  dd lo = fast_two_sum(h, l - e);
+  dd hi = fast_two_sum(h, l + e);
+  float a = cvt_f32_mode<RM>(ro53(lo.hi, lo.lo));
+  float b = cvt_f32_mode<RM>(ro53(hi.hi, hi.lo));
+  ok = a == b;
+  return b;
+}
+
+// The same with an absolute error bound e.
+template <int RM>
+__device__ __forceinline__ float round_f32_dd_abs_mode(double h, double l, double e, bool& ok) {
+  dd lo = fast_two_sum(h, l - e);
+  dd hi = fast_two_sum(h, l + e);
+  float a = cvt_f32_mode<RM>(ro53(lo.hi, lo.lo));
+  float b = cvt_f32_mode<RM>(ro53(hi.hi, hi.lo));
+  ok = a == b;
+  return b;
+}
+
+// The rounding in mode RM of base + d, for a binary32 base and a d of sign s
+// (+1 or -1) smaller than a quarter ulp of base (tiny arguments: sin x just
+// below x, cos x just below 1, ...).
+template <int RM>
+__device__ __forceinline__ float round_near_float(float base, int s) {
+  if (RM == RM_RU) return s > 0 ? f32_next_up(base) : base;
+  if (RM == RM_RD) return s < 0 ? f32_next_down(base) : base;
+  if (RM == RM_RZ) {
+    if (base > 0.0f) return s < 0 ? f32_next_down(base) : base;
+    return s > 0 ? f32_next_up(base) : base;
+  }
+  return base;
+}
+
 }  // namespace cr

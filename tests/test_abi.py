@@ -73,6 +73,23 @@ def test_argument_validation(L):
         assert L.cr_available(f, 2) == 0
 
 
+def test_rounding_mode_validation(L):
+    """Directed modes: binary32 functions with the binary64-internal
+    implementation only; batches round to nearest."""
+    from paper_2605_15547_amd import crmath as C
+    vp = ctypes.c_void_p
+    ev = L.cr_eval_ex
+    for fl in (C.FLAG_ROUND_TOWARD_ZERO, C.FLAG_ROUND_UP, C.FLAG_ROUND_DOWN):
+        assert ev(64, 0, fl, vp(0x1000), vp(0x2000), 8, None) == -5   # binary64 exp
+        assert ev(80, 0, fl, vp(0x1000), vp(0x2000), 8, None) == -5   # complex
+        assert ev(65, 3, fl, vp(0x1000), vp(0x2000), 8, None) == -5   # log, 128-entry table
+        assert ev(0, 2, fl, vp(0x1000), vp(0x2000), 8, None) == -5    # split implementation
+        plan = vp()
+        arr = C._requests([("expf", 0x1000, 0x2000, 8)])
+        assert L.cr_batch_plan_create(arr, 1, fl, ctypes.byref(plan)) == -5
+        assert plan.value is None
+
+
 def test_dft_validation(L):
     """cr_dft rejects bad arguments before launching anything."""
     vp = ctypes.c_void_p
