@@ -234,7 +234,10 @@ int cr_eval_batch_noalloc(const cr_request *reqs, int32_t num, void *stream);
  *   escapes        elements whose accurate path could not certify the
  *                  rounding (expected 0; their output is still the accurate
  *                  path's result); escape_index[] holds the first ones, as
- *                  element indices within their call. */
+ *                  element indices within their call (for a batch:
+ *                  (request index << 32) | element index within the
+ *                  request, the request index counted in the caller's
+ *                  array). */
 typedef struct {
   uint64_t elems;
   uint64_t fallback_lanes;

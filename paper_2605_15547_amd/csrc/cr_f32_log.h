@@ -11,10 +11,10 @@
 // t in [-1/32, 1/16].  c_j = 1 on the two sub-intervals next to 1, so for x
 // near 1 the result is K t + t Q(t) with no cancellation.  log1pf reduces
 // u = RN(1 + x) the same way.  1 + x is exact for binary32 x unless |x| < 2^-29
-// or x >= 2^29.  For |x| < 2^-29, u is within 2^-29 of 1, so e' = 0 and c_j = 1,
-// and the fast path takes t = x exactly; for x >= 2^29, log(u) differs from
-// log(1 + x) by less than 2^-53 while the result exceeds 20 (ulp 2^-48).  The
-// accurate path adds the rounding error of u, scaled like m, to t instead.
+// or x >= 2^29.  The fast path returns x itself for |x| < 2^-25 (the correctly
+// rounded result there, see log1p_special_fast); for x >= 2^29, log(u) differs
+// from log(1 + x) by less than 2^-53 while the result exceeds 20 (ulp 2^-48).
+// The accurate path adds the rounding error of u, scaled like m, to t instead.
 //
 // The binary64 fast path ends with the rounding test of cr_round.h; lanes that
 // fail it run the accurate double-double path below (the log1p series to degree
@@ -136,7 +136,6 @@ __device__ __forceinline__ LogSetup log_setup(float xf, const LogTab& tb) {
   S.c = tb.row[j].c;
   S.L = tb.row[j].L;
   S.t = fma(S.m, S.c, -1.0);
-  if (K == LOGK_1P) S.t = fabsf(xf) < 0x1p-29f ? x : S.t;  // 1 + x inexact: t = x
   return S;
 }
 
@@ -170,14 +169,20 @@ __device__ __forceinline__ bool log_special_fast(float xf, float& res) {
   return __builtin_amdgcn_class(xf, 0x27f);  // all classes but +denormal, +normal
 }
 
-// The same for log1pf, through the hardware logarithm of 1 + x (binary32):
-// NaN (1 + x keeps the payload and quiets it), x = -1 (-inf) and +inf come out
-// right; x < -1 needs the positive default NaN and x = +-0 the signed zero.
+// The fast path's special cases for log1pf, without a transcendental
+// instruction: NaN (returned quieted: canonicalize quiets a signaling NaN and
+// keeps the payload and sign), +inf (itself), x = -1 (-inf), x < -1 (the
+// default NaN), and the tiny arguments |x| < 2^-25, zeros and subnormals
+// included, whose result is x itself: log1p x = x - x^2/2 + ... lies within
+// x^2/2 <= 2^-26 |x| of x, below half the spacing of the binary32 numbers on
+// either side of x (at least 2^-24 |x|), so it rounds to x.  With these out of
+// the way 1 + x is exact in binary64 for every remaining x below 2^29, and the
+// result is a normal binary32 number, as the bit test requires.
 __device__ __forceinline__ bool log1p_special_fast(float xf, float& res) {
-  const float h = __builtin_amdgcn_logf(1.0f + xf);
-  res = xf < -1.0f ? bits_f32(0x7fc00000u) : (xf == 0.0f ? xf : h);
-  // NaN, infinities, zeros (class mask), and everything at or below -1
-  return __builtin_amdgcn_class(xf, 0x267) | (xf <= -1.0f);
+  const float q = __builtin_canonicalizef(xf);
+  res = xf <= -1.0f ? (xf == -1.0f ? -INFINITY : bits_f32(0x7fc00000u)) : q;
+  // NaN and infinities (class mask), tiny arguments, everything at or below -1
+  return __builtin_amdgcn_class(xf, 0x207) | (fabsf(xf) < 0x1p-25f) | (xf <= -1.0f);
 }
 
 template <int K>
@@ -192,7 +197,6 @@ __device__ __forceinline__ float log_fast(float xf, const LogTab& tb, bool& ok) 
   // logf, log2f and log10f round to normal binary32 numbers (or to +0 at 1),
   // log1pf too except for subnormal x, which are left to the accurate path
   float res = round_f32_bits<LOG_TEST_E>(yh, ok);
-  if (K == LOGK_1P) ok = ok && fabs(yh) >= 0x1p-126;
   float sp;
   if (K == LOGK_1P ? log1p_special_fast(xf, sp) : log_special_fast(xf, sp)) {
     res = sp;

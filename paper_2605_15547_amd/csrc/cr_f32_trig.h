@@ -147,6 +147,22 @@ __device__ __forceinline__ bool trig_special(float xf, float& res, int kind) {
   return nan | inf | zero;
 }
 
+// The fast path's special cases, with the tiny arguments folded in: for
+// |x| < 2^-12 (zeros and subnormals included) sin x = x - x^3/6 + ... and
+// tan x = x + x^3/3 + ... lie within x^2/3 < 2^-25.6 |x| of x and cos x =
+// 1 - x^2/2 + ... within 2^-25 of 1, less than half the spacing of the
+// binary32 numbers next to x (at least 2^-24 |x|) or below 1 (2^-24), so the
+// correctly rounded results are x and 1.  NaN is returned quieted
+// (canonicalize quiets it and keeps the payload), infinities give the
+// default NaN.  One class test and a magnitude compare pick these lanes.
+__device__ __forceinline__ bool trig_special_fast(float xf, float& res, int kind) {
+  const bool inf = fabsf(xf) == INFINITY;
+  const float q = __builtin_canonicalizef(xf);
+  const float t = (kind == TRIGK_COS && xf == xf) ? 1.0f : q;
+  res = inf ? bits_f32(0x7fc00000u) : t;
+  return __builtin_amdgcn_class(xf, 0x207) | (fabsf(xf) < 0x1p-12f);
+}
+
 // Fast path: binary64 sin and cos of x with absolute error bounds.
 struct TrigFast {
   double s, c, es, ec;  // values and error bounds
@@ -190,27 +206,41 @@ __device__ __forceinline__ TrigFast trig_fast_core(float xf, const TrigTab& tb) 
     q = 0;
   }
   double r2 = r * r;
-  double ps = SIN_S[SIN_S_DEG];
-#pragma unroll
-  for (int i = SIN_S_DEG - 1; i >= 0; i--) ps = fma(ps, r2, SIN_S[i]);
-  double pc = COS_C[COS_C_DEG];
-#pragma unroll
-  for (int i = COS_C_DEG - 1; i >= 0; i--) pc = fma(pc, r2, COS_C[i]);
+  double ps = fma(fma(SIN_S2[2], r2, SIN_S2[1]), r2, SIN_S2[0]);
+  double pc = fma(fma(COS_C2[2], r2, COS_C2[1]), r2, COS_C2[0]);
   double sr = fma(r * r2, ps, r);  // sin r
   double cm1 = r2 * pc;            // cos r - 1
   SinCosTheta th = theta_of(q, tb);
   TrigFast o;
-  o.s = th.sh + (th.sl + fma(th.sh, cm1, th.ch * sr));
-  o.c = th.ch + (th.cl + fma(th.ch, cm1, -(th.sh * sr)));
-  // Error bounds: r is within 2^-52 |r| + 2^-66 of f pi/32 after reduction
-  // (f within 2^-63 in units of N, times pi/32: 2^-66.35; r exact when
-  // |x| < pi/64); the polynomials are within 2^-66; the sums add
-  // a few units of 2^-53 |result| (|sin x|, |cos x| >= 0.049 unless j = 0, in
-  // which case the table terms are exact).  Bound: 2^-49 |y| + 2^-63.
-  double abs_term = small ? 0.0 : 0x1p-63;
-  o.es = fma(fabs(o.s), 0x1p-49, abs_term);
-  o.ec = fma(fabs(o.c), 0x1p-49, abs_term);
+  // the table's high parts only (sin and cos of j pi/32 to 2^-54)
+  o.s = th.sh + fma(th.sh, cm1, th.ch * sr);
+  o.c = th.ch + fma(th.ch, cm1, -(th.sh * sr));
+  // Error bounds, absolute: r within 2^-52 |r| + 2^-66.35 (reduction, f to
+  // 2^-63 in units of N; exact when |x| < pi/64); the degree-2 corrections
+  // within 2^-50.1 (cos) and 2^-57.6 (sin) -- the bound tests re-derive both;
+  // the table entries within 2^-54 each; three roundings of terms below 0.05
+  // and the final one of y.  With |sin x|, |cos x| >= 0.049 unless j = 0 this
+  // is below 2^-49.95 absolute, i.e. 2^-45.6 |y|.  For j = 0 the table terms
+  // are exactly 0 and +-1 and y is +-sin r (within 2^-57.6 + 2^-51.9 |y| +
+  // 2^-66.35) or +-cos r (within 2^-50.1, |y| > 0.99).  Bound used:
+  // 2^-45 |y| + 2^-57.
+  o.es = fma(fabs(o.s), 0x1p-45, 0x1p-57);
+  o.ec = fma(fabs(o.c), 0x1p-45, 0x1p-57);
   return o;
+}
+
+// The rounding test of the sin and cos fast paths, read off the bits of yh:
+// for |yh| >= 2^-12 the bound above is below 2^-44 |yh| (the absolute term is
+// then below 2^-45 |yh|), i.e. below 512 ulps of yh (ulps of 2^-53 |yh| and
+// up), so a binary32 midpoint can lie within the error only when the 29 low
+// bits of yh come within 512 of the midpoint pattern 2^28 (cr_round.h,
+// round_f32_bits).  Results below 2^-12 in magnitude (x within about 2^-12 of
+// a zero of sin or cos: about 1.5 10^-4 of random arguments) go to the
+// accurate path.
+__device__ __forceinline__ float round_trig_fast(double yh, bool& ok) {
+  float r = round_f32_bits<512>(yh, ok);
+  ok = ok && fabs(yh) >= 0x1p-12;
+  return r;
 }
 
 // ------------------------------------------------------------ accurate path
@@ -338,9 +368,9 @@ __device__ __forceinline__ float trig_fast(float xf, const TrigTab& tb, bool& ok
   bool neg = xf < 0.0f;
   float res;
   if (KIND == TRIGK_COS) {
-    res = round_f32_fast_abs(F.c, F.ec, ok);
+    res = round_trig_fast(F.c, ok);
   } else if (KIND == TRIGK_SIN) {
-    res = round_f32_fast_abs(neg ? -F.s : F.s, F.es, ok);
+    res = round_trig_fast(neg ? -F.s : F.s, ok);
   } else {
     double t = F.s / F.c;
     // relative error of the quotient plus the absolute errors of s and c
@@ -350,7 +380,7 @@ __device__ __forceinline__ float trig_fast(float xf, const TrigTab& tb, bool& ok
     res = round_f32_fast_abs(neg ? -t : t, e, ok);
   }
   float sp;
-  if (trig_special(xf, sp, KIND)) {
+  if (trig_special_fast(xf, sp, KIND)) {
     res = sp;
     ok = true;
   }
@@ -361,13 +391,13 @@ __device__ __forceinline__ float trig_fast(float xf, const TrigTab& tb, bool& ok
 __device__ __forceinline__ float sincos_fast(float xf, const TrigTab& tb, float& c, bool& ok) {
   TrigFast F = trig_fast_core(xf, tb);
   bool ok1, ok2;
-  float s = round_f32_fast_abs(xf < 0.0f ? -F.s : F.s, F.es, ok1);
-  c = round_f32_fast_abs(F.c, F.ec, ok2);
+  float s = round_trig_fast(xf < 0.0f ? -F.s : F.s, ok1);
+  c = round_trig_fast(F.c, ok2);
   ok = ok1 && ok2;
   float sp;
-  if (trig_special(xf, sp, TRIGK_SIN)) {
+  if (trig_special_fast(xf, sp, TRIGK_SIN)) {
     s = sp;
-    trig_special(xf, c, TRIGK_COS);
+    trig_special_fast(xf, c, TRIGK_COS);
     ok = true;
   }
   return s;

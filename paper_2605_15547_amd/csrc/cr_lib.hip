@@ -535,8 +535,9 @@ __global__ void __launch_bounds__(BLOCK)
   }
 }
 
-// sincosf: the map kernel with two planar outputs (sin block, cos block), both
-// 16-byte aligned (the host checks; otherwise the scalar form below runs).
+// sincosf: the map kernel with two planar outputs (sin block, cos block); the
+// input and the sine block 16-byte aligned (the host checks; otherwise the
+// scalar form below runs).
 template <class SC, bool FINAL = false>
 __device__ __forceinline__ void flush_queue_sincos(Deferred& q, const typename SC::Tab& tab,
                                                    float* os, float* oc, DevStats* st,
@@ -549,9 +550,12 @@ __device__ __forceinline__ void flush_queue_sincos(Deferred& q, const typename S
   });
 }
 
-template <class SC>
+// CVEC: the cosine block is 16-byte aligned as well (n a multiple of 4);
+// otherwise its four values per vector are stored one by one (still
+// contiguous across the lanes of a wave).
+template <class SC, bool CVEC>
 __global__ void __launch_bounds__(BLOCK)
-    k_map_sincos(const float4* in, float4* outs, float4* outc, long long n4, DevStats* st,
+    k_map_sincos(const float4* in, float4* outs, float* outc, long long n4, DevStats* st,
                  unsigned flags, long long elem_base) {
   __shared__ typename SC::Tab tab;
   __shared__ Deferred q;
@@ -604,7 +608,15 @@ __global__ void __launch_bounds__(BLOCK)
       long long i = base + (long long)u * BLOCK;
       if (i < n4) {
         st_stream(outs + i, v[u]);
-        st_stream(outc + i, c4[u]);
+        if (CVEC) {
+          st_stream(reinterpret_cast<float4*>(outc) + i, c4[u]);
+        } else {
+          float* p = outc + 4 * i;
+          p[0] = c4[u].x;
+          p[1] = c4[u].y;
+          p[2] = c4[u].z;
+          p[3] = c4[u].w;
+        }
       }
     }
     if (iter % SC::qcheck == SC::qcheck - 1) {
@@ -612,13 +624,11 @@ __global__ void __launch_bounds__(BLOCK)
       const unsigned nq = q.n;
       __syncthreads();
       if (nq > QFLUSH)
-        flush_queue_sincos<SC>(q, tab, reinterpret_cast<float*>(outs), reinterpret_cast<float*>(outc),
-                           st, elem_base);
+        flush_queue_sincos<SC>(q, tab, reinterpret_cast<float*>(outs), outc, st, elem_base);
     }
   }
   __syncthreads();
-  flush_queue_sincos<SC, true>(q, tab, reinterpret_cast<float*>(outs),
-                               reinterpret_cast<float*>(outc), st, elem_base);
+  flush_queue_sincos<SC, true>(q, tab, reinterpret_cast<float*>(outs), outc, st, elem_base);
 }
 
 template <class SC>
@@ -1155,6 +1165,7 @@ struct BReq {
   int func;
   int aligned;  // in and out (and the cos block for sincosf) are 16-byte aligned
   int key;      // func + BSPLIT for the binary32-only implementation
+  int orig;     // index of the request in the caller's array
 };
 constexpr int BSPLIT = 32;
 struct BTile {
@@ -1184,10 +1195,16 @@ struct BDeferred {
   float x[QCAP];
 };
 
+// Escapes of a batch are recorded as (request << 32) | element index within
+// the request.
+__device__ __forceinline__ long long batch_escape_id(unsigned req, unsigned idx) {
+  return (long long)(((unsigned long long)req << 32) | idx);
+}
+
 template <class Op>
 __device__ __forceinline__ void batch_enqueue(BDeferred& q, const typename Op::Tab& tab,
-                                              unsigned req, unsigned idx, float x, float& res,
-                                              DevStats* st) {
+                                              unsigned req, unsigned orig, unsigned idx, float x,
+                                              float& res, DevStats* st) {
   unsigned pos = atomicAdd(&q.n, 1u);
   if (pos < QCAP) {
     q.req[pos] = req;
@@ -1197,7 +1214,7 @@ __device__ __forceinline__ void batch_enqueue(BDeferred& q, const typename Op::T
     AccResult a = Op::accurate(x, tab);
     res = a.r;
     atomicAdd(&q.lanes, 1u);
-    if (!a.ok) note_escape(st, (long long)idx);
+    if (!a.ok) note_escape(st, batch_escape_id(orig, idx));
   }
 }
 
@@ -1221,7 +1238,8 @@ __device__ __forceinline__ void batch_tile(BReq R, BTile T, const typename Op::T
           bool ok;
           float x = e[c];
           e[c] = Op::fast(x, tab, ok);
-          if (!ok || force) batch_enqueue<Op>(q, tab, T.req, base + 4 * i + c, x, e[c], st);
+          if (!ok || force)
+            batch_enqueue<Op>(q, tab, T.req, R.orig, base + 4 * i + c, x, e[c], st);
         }
         st_stream(reinterpret_cast<float4*>(out) + i, v);
       }
@@ -1231,7 +1249,7 @@ __device__ __forceinline__ void batch_tile(BReq R, BTile T, const typename Op::T
       bool ok;
       float x = in[i];
       float r = Op::fast(x, tab, ok);
-      if (!ok || force) batch_enqueue<Op>(q, tab, T.req, base + i, x, r, st);
+      if (!ok || force) batch_enqueue<Op>(q, tab, T.req, R.orig, base + i, x, r, st);
       out[i] = r;
     }
   } else {
@@ -1239,7 +1257,7 @@ __device__ __forceinline__ void batch_tile(BReq R, BTile T, const typename Op::T
       bool ok;
       float x = in[i];
       float r = Op::fast(x, tab, ok);
-      if (!ok || force) batch_enqueue<Op>(q, tab, T.req, base + i, x, r, st);
+      if (!ok || force) batch_enqueue<Op>(q, tab, T.req, R.orig, base + i, x, r, st);
       out[i] = r;
     }
   }
@@ -1253,10 +1271,10 @@ __device__ __forceinline__ void batch_tile_sincos(BReq R, BTile T, const typenam
   float* oc = reinterpret_cast<float*>(R.out) + R.n + T.start;
   const int cnt = T.count;
   const unsigned base = (unsigned)T.start;
-  for (int i = threadIdx.x; i < cnt; i += BLOCK) {
+  // one element: fast path, queue or accurate path in place
+  auto one = [&](int i, float x, float& sv, float& c) {
     bool ok;
-    float x = in[i], c;
-    float sv = SC::fast(x, tab, c, ok);
+    sv = SC::fast(x, tab, c, ok);
     if (!ok || force) {
       unsigned pos = atomicAdd(&q.n, 1u);
       if (pos < QCAP) {
@@ -1268,9 +1286,31 @@ __device__ __forceinline__ void batch_tile_sincos(BReq R, BTile T, const typenam
         sv = a.s;
         c = a.c;
         atomicAdd(&q.lanes, 1u);
-        if (!a.ok) note_escape(st, (long long)(base + i));
+        if (!a.ok) note_escape(st, batch_escape_id(R.orig, base + i));
       }
     }
+  };
+  int i0 = 0;
+  if (R.aligned) {  // input, sine block and cosine block 16-byte aligned
+    const int n4 = cnt >> 2;
+#pragma unroll
+    for (int u = 0; u < TILE_U; u++) {
+      int i = threadIdx.x + u * BLOCK;
+      if (i < n4) {
+        float4 v = ld_stream(reinterpret_cast<const float4*>(in) + i), cv;
+        float* e = reinterpret_cast<float*>(&v);
+        float* ec = reinterpret_cast<float*>(&cv);
+#pragma unroll
+        for (int c = 0; c < 4; c++) one(4 * i + c, e[c], e[c], ec[c]);
+        st_stream(reinterpret_cast<float4*>(os) + i, v);
+        st_stream(reinterpret_cast<float4*>(oc) + i, cv);
+      }
+    }
+    i0 = 4 * n4;
+  }
+  for (int i = i0 + threadIdx.x; i < cnt; i += BLOCK) {
+    float sv, c;
+    one(i, in[i], sv, c);
     os[i] = sv;
     oc[i] = c;
   }
@@ -1284,7 +1324,7 @@ __device__ __forceinline__ void batch_flush_one(BDeferred& q, const typename Op:
     AccResult a = Op::accurate(q.x[k], tab);
     float* out = reinterpret_cast<float*>(reqs[q.req[k]].out);
     out[q.idx[k]] = a.r;
-    if (!a.ok) note_escape(st, (long long)q.idx[k]);
+    if (!a.ok) note_escape(st, batch_escape_id(reqs[q.req[k]].orig, q.idx[k]));
   });
 }
 
@@ -1297,7 +1337,7 @@ __device__ __forceinline__ void batch_flush_one_sincos(BDeferred& q, const typen
     float* out = reinterpret_cast<float*>(R.out);
     out[q.idx[k]] = a.s;
     out[R.n + q.idx[k]] = a.c;
-    if (!a.ok) note_escape(st, (long long)q.idx[k]);
+    if (!a.ok) note_escape(st, batch_escape_id(reqs[q.req[k]].orig, q.idx[k]));
   });
 }
 
@@ -1534,7 +1574,10 @@ int launch_sincos(const float* in, float* out, size_t n, hipStream_t s, unsigned
                   DevStats* st, int grid) {
   float* outc = out + n;
   uintptr_t ai = (uintptr_t)in, ao = (uintptr_t)out, ac = (uintptr_t)outc;
-  bool vec = (ai & 15) == 0 && (ao & 15) == 0 && (ac & 15) == 0;
+  // vector body when the input and the sine block are 16-byte aligned; the
+  // cosine block (at out + n) is stored by vectors too when it is aligned
+  bool vec = (ai & 15) == 0 && (ao & 15) == 0;
+  bool cvec = (ac & 15) == 0;
   size_t body4 = vec ? n / 4 : 0;
   size_t done4 = 0;
   while (done4 < body4) {
@@ -1543,10 +1586,11 @@ int launch_sincos(const float* in, float* out, size_t n, hipStream_t s, unsigned
     size_t tiles = (chunk4 + BLOCK * TILE_U - 1) / (BLOCK * TILE_U);
     size_t g = tiles < (size_t)grid ? tiles : (size_t)grid;
     size_t off = 4 * done4;
-    hipLaunchKernelGGL(k_map_sincos<SC>, dim3((unsigned)g), dim3(BLOCK), 0, s,
+    auto k = cvec ? k_map_sincos<SC, true> : k_map_sincos<SC, false>;
+    hipLaunchKernelGGL(k, dim3((unsigned)g), dim3(BLOCK), 0, s,
                        reinterpret_cast<const float4*>(in + off),
-                       reinterpret_cast<float4*>(out + off), reinterpret_cast<float4*>(outc + off),
-                       (long long)chunk4, st, flags, (long long)off);
+                       reinterpret_cast<float4*>(out + off), outc + off, (long long)chunk4, st,
+                       flags, (long long)off);
     done4 += chunk4;
   }
   size_t off = 4 * body4;
@@ -1886,6 +1930,7 @@ int build_tables(const cr_request* reqs, int32_t num, std::vector<BReq>& hr,
     q.n = r.n;
     q.func = r.func_id;
     q.key = key(order[oi]);
+    q.orig = order[oi];
     uintptr_t a = (uintptr_t)r.in, b = (uintptr_t)r.out;
     uintptr_t c = b + 4 * (uintptr_t)r.n;
     q.aligned = ((a | b) & 15) == 0 && (r.func_id != CR_SINCOSF || (c & 15) == 0);

@@ -326,32 +326,22 @@ def gen_trig():
         emit("  {%s, %s, %s, %s}," % (hexd(sh), hexd(sl), hexd(ch), hexd(cl)))
     emit("};")
     rho = mp.pi / 64 * mp.mpf("1.0001")
-    # sin r = r + r^3 S(r^2); cos r - 1 = r^2 C(r^2)
-    for name, g, w, lo_deg in (
-            ("SIN_S", lambda u: (mp.sin(mp.sqrt(u)) / mp.sqrt(u) - 1) / u if u != 0 else mp.mpf(-1) / 6,
-             lambda u: u * mp.sqrt(u), 2),
-            ("COS_C", lambda u: (mp.cos(mp.sqrt(u)) - 1) / u if u != 0 else mp.mpf(-1) / 2,
-             lambda u: u, 2)):
-        for deg in range(lo_deg, 7):
-            cs = lawson_fit(g, w, mp.mpf(0), rho * rho, list(range(deg + 1)), npts=120, iters=16)
-            cd = [d(v) for v in cs]
-            if name == "SIN_S":
-                err = max_err(lambda r: mp.sin(r) - r - r ** 3 * sum(mp.mpf(cd[k]) * r ** (2 * k)
-                                                                       for k in range(len(cd))),
-                              mp.mpf(0), rho)
-            else:
-                err = max_err(lambda r: mp.cos(r) - 1 - r ** 2 * sum(mp.mpf(cd[k]) * r ** (2 * k)
-                                                                      for k in range(len(cd))),
-                              mp.mpf(0), rho)
-            if err < mp.mpf(2) ** -66:
-                break
-        mk = B.sin_minus_r if name == "SIN_S" else B.cos_minus_1
+    # fast path: sin r = r + r^3 S2(r^2), cos r - 1 = r^2 C2(r^2), degree 2 in
+    # r^2, for the fast path's error budget (its rounding test allows 2^-45
+    # relative)
+    for name, g, w in (
+            ("SIN_S2", lambda u: (mp.sin(mp.sqrt(u)) / mp.sqrt(u) - 1) / u if u != 0 else mp.mpf(-1) / 6,
+             lambda u: u * mp.sqrt(u)),
+            ("COS_C2", lambda u: (mp.cos(mp.sqrt(u)) - 1) / u if u != 0 else mp.mpf(-1) / 2,
+             lambda u: u)):
+        cs = lawson_fit(g, w, mp.mpf(0), rho * rho, [0, 1, 2], npts=120, iters=16)
+        cd = [d(v) for v in cs]
+        mk = B.sin_minus_r if name == "SIN_S2" else B.cos_minus_1
         bound = B.sup_bound(mk([mp.mpf(v) for v in cd], rho))
-        emit("// %s: |r| <= pi/64; |approximation error| <= 2^%.2f (absolute, proven)"
-             % ("sin r = r + r^3 S(r^2)" if name == "SIN_S" else "cos r - 1 = r^2 C(r^2)",
+        emit("// %s (fast path): |r| <= pi/64; |approximation error| <= 2^%.2f (absolute, proven)"
+             % ("sin r = r + r^3 S2(r^2)" if name == "SIN_S2" else "cos r - 1 = r^2 C2(r^2)",
                 log2_of(bound)))
-        emit_arr(name, cd, "coefficients (degree %d in r^2)" % (len(cd) - 1))
-        emit("#define %s_DEG %d" % (name, len(cd) - 1))
+        emit_arr(name, cd, "coefficients (degree 2 in r^2)")
     # accurate path: Taylor coefficients (-1)^k / (2k+1)! and (-1)^k / (2k)!
     N = 9
     emit("#define TRIG_TAYLOR_N %d" % N)
