@@ -79,10 +79,12 @@ enum cr_func {
 enum cr_impl {
   CR_IMPL_AUTO = 0,         /* library default (currently F64_INTERNAL) */
   CR_IMPL_F64_INTERNAL = 1, /* binary64 fast path + double-double accurate path */
-  CR_IMPL_SPLIT_F32 = 2,    /* binary32-only float-float fast path; lanes that fail its
-                             * rounding test take the binary64 accurate path.  Built for
-                             * the functions where cr_available(f, CR_IMPL_SPLIT_F32)
-                             * is 1; the others give CR_E_IMPL */
+  CR_IMPL_SPLIT_F32 = 2,    /* binary32 arithmetic only, no binary64 operation: a
+                             * float-float fast path, and a triple-float accurate step
+                             * for the lanes that fail its rounding test (same results
+                             * as F64_INTERNAL).  Round to nearest only.  Built for the
+                             * functions where cr_available(f, CR_IMPL_SPLIT_F32) is 1;
+                             * the others give CR_E_IMPL */
   CR_IMPL_LOG128 = 3        /* CR_LOG only: the paper's cr_log main path (Sec. II-B) with
                              * one 128-entry table of scaled 64-bit integers, T_j =
                              * log1p(r_j)/r_j - 1 for the 128 reciprocals r_j + 1 of 8

@@ -32,6 +32,7 @@
 #include "cr_split_rsqrt.h"
 #include "cr_split_atan.h"
 #include "cr_split_hyp.h"
+#include "cr_split_acc.h"
 
 using namespace cr;
 
@@ -149,7 +150,7 @@ struct SinCosSplit {
     return ssincos_fast(x, t, c, ok);
   }
   static __device__ __forceinline__ AccResult2 accurate(float x, const Tab& t) {
-    return sincos_accurate(x, t.acc);
+    return ssincos_acc(x, t.w);
   }
 };
 
@@ -175,7 +176,7 @@ struct OpSAtan {
     return satan_fast<KIND>(x, t, ok);
   }
   static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
-    return atan_accurate<KIND>(x, t.acc);
+    return satan_acc<KIND>(x);
   }
 };
 
@@ -188,7 +189,7 @@ struct OpSHyp {
     return shyp_fast<KIND>(x, t, ok);
   }
   static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
-    return hyp_accurate<KIND>(x, t.acc);
+    return shyp_acc<KIND>(x);
   }
 };
 
@@ -201,12 +202,12 @@ struct OpSTrig {
     return strig_fast<KIND>(x, t, ok);
   }
   static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
-    return trig_accurate<KIND>(x, t.acc);
+    return strig_acc<KIND>(x, t.w);
   }
 };
 
-// binary32-only (float-float) fast paths; failing lanes take the accurate
-// path of the binary64 kernels
+// binary32-only (float-float) fast paths; failing lanes take the triple-float
+// step (cr_split_acc.h): no binary64 operation on the whole path
 template <int K>
 struct OpSExp {
   using Tab = SExpTab;
@@ -216,7 +217,7 @@ struct OpSExp {
     return sexp_fast<K>(x, t, ok);
   }
   static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
-    return exp_accurate<K>(x, t.acc);
+    return sexp_acc<K>(x);
   }
 };
 
@@ -229,7 +230,7 @@ struct OpSLog {
     return slog_fast<K>(x, t, ok);
   }
   static __device__ __forceinline__ AccResult accurate(float x, const Tab& t) {
-    return log_accurate<K>(x, t.acc);
+    return slog_acc<K>(x);
   }
 };
 

@@ -10,8 +10,8 @@
 // quotient takes one float-float correction step, and t and t^3/3 are
 // float-float.  For j = 0 the table term is 0 and atan(Y/X) = atan(t) keeps
 // its full relative accuracy (small arguments of atan and asin, acos near 1).
-// Rounding test: relative bound 2^-42; failing lanes take the accurate path of
-// cr_f32_atan.h.
+// Rounding test: relative bound 2^-42; failing lanes take the triple-float
+// step of cr_split_acc.h.
 #pragma once
 #include "cr_f32_atan.h"
 #include "cr_split.h"
@@ -21,12 +21,10 @@ namespace cr {
 
 struct SAtanTab {
   float4 t[16];
-  AtanTab acc;  // for the accurate path
 };
 
 __device__ __forceinline__ void satan_tab_load(SAtanTab& t, int tid) {
   if (tid < 16) t.t[tid] = SATAN_T[tid];
-  atan_tab_load(t.acc, tid);
 }
 
 // atan(Y/X) as a float-float for float-float Y, X >= 0, not both zero

@@ -21,7 +21,7 @@
 //   rounded (m = 0: u = W, relative bound 2^-42; otherwise absolute 2^-45) and
 //   the result is u 2^m.  For |x| < ln2/512, k = 0 and W = q: no
 //   cancellation at all near 0.
-// Lanes that fail the test take the accurate path of cr_f32_exp.h.
+// Lanes that fail the test take the triple-float step of cr_split_acc.h.
 #pragma once
 #include "cr_f32_exp.h"
 #include "cr_split.h"
@@ -31,7 +31,6 @@ namespace cr {
 
 struct SExpTab {
   float2 t1[16], t2[16];
-  ExpTab acc;  // for the accurate path
 };
 
 template <int K>
@@ -40,7 +39,6 @@ __device__ __forceinline__ void sexp_tab_load(SExpTab& t, int tid) {
     t.t1[tid] = (K == EXPK_EM1) ? SEXP_D1[tid] : SEXP_T1[tid];
     t.t2[tid] = (K == EXPK_EM1) ? SEXP_D2[tid] : SEXP_T2[tid];
   }
-  exp_tab_load(t.acc, tid);
 }
 
 // k (as a float) and r = x ln b - k ln2/256 as a normalised float-float

@@ -13,8 +13,8 @@
 // The clamps (|x| <= 100 for sinh and cosh, 20 for tanh) keep m in range while
 // the results still overflow or round to 1; beyond m = 30 the e^-a term is
 // below 2^-60 of the result and its scale is frozen at 2^-60 (no underflow).
-// Rounding test: relative bound 2^-42; failing lanes take the accurate path of
-// cr_f32_hyp.h.
+// Rounding test: relative bound 2^-42; failing lanes take the triple-float
+// step of cr_split_acc.h.
 #pragma once
 #include "cr_f32_hyp.h"
 #include "cr_split_exp.h"
@@ -23,7 +23,6 @@ namespace cr {
 
 struct SHypTab {
   float2 t1[16], t2[16], d1[16], d2[16];
-  ExpTab acc;  // for the accurate path
 };
 
 __device__ __forceinline__ void shyp_tab_load(SHypTab& t, int tid) {
@@ -33,7 +32,6 @@ __device__ __forceinline__ void shyp_tab_load(SHypTab& t, int tid) {
     t.d1[tid] = SEXP_D1[tid];
     t.d2[tid] = SEXP_D2[tid];
   }
-  exp_tab_load(t.acc, tid);
 }
 
 template <int KIND>

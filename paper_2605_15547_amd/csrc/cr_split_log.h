@@ -19,7 +19,7 @@
 // full relative accuracy (log1p of tiny x included).
 // The rounding test uses a relative bound of 2^-43 (table entries 2^-49 of at
 // most 0.29, the float-float sums a few 2^-49, against results >= 2^-9.2 when
-// C != 1); failing lanes take the accurate path of cr_f32_log.h.
+// C != 1); failing lanes take the triple-float step of cr_split_acc.h.
 #pragma once
 #include "cr_f32_log.h"
 #include "cr_split.h"
@@ -30,7 +30,6 @@ namespace cr {
 struct SLogTab {
   float c1[16], c2[16];
   float2 L1[16], L2[16];
-  LogTab acc;  // for the accurate path
 };
 
 template <int K>
@@ -41,7 +40,6 @@ __device__ __forceinline__ void slog_tab_load(SLogTab& t, int tid) {
     t.L1[tid] = SLOG_L1[tid];
     t.L2[tid] = SLOG_L2[tid];
   }
-  log_tab_load<K>(t.acc, tid);
 }
 
 // NaN (quieted), zero and negative arguments, +inf, log1p(+-0) = +-0

@@ -16,7 +16,8 @@
 // tan x = sin x / cos x by a float-float division.
 // Rounding tests: relative bound 2^-43 (2^-42 for tan); for reduced arguments
 // an absolute floor of 2^-149 sends a (theoretical) fully cancelled f to the
-// accurate path.  Failing lanes take the accurate path of cr_f32_trig.h.
+// accurate path.  Failing lanes take the triple-float
+// step of cr_split_acc.h.
 #pragma once
 #include "cr_f32_trig.h"
 #include "cr_split.h"
@@ -26,12 +27,12 @@ namespace cr {
 
 struct STrigTab {
   float4 sc[16];
-  TrigTab acc;  // accurate path; its 2/pi words also serve the reduction
+  unsigned w[10];  // the words of 2/pi of the Payne-Hanek reduction
 };
 
 __device__ __forceinline__ void strig_tab_load(STrigTab& t, int tid) {
   if (tid < 16) t.sc[tid] = STRIG_T[tid];
-  trig_tab_load(t.acc, tid);
+  if (tid < 10) t.w[tid] = TWO_OVER_PI_W[tid];
 }
 
 // float-float product a b (|result| error ~2^-47 relative)
@@ -49,7 +50,7 @@ __device__ __forceinline__ STrigCore strig_core(float xf, const STrigTab& tb) {
   uint32_t ax = f32_bits(xf) & 0x7fffffffu;
   float axf = bits_f32(ax);
   bool small = axf < STRIG_PI64;
-  Reduced R = payne_hanek(ax, tb.acc.w);
+  Reduced R = payne_hanek(ax, tb.w);
   // |f| as a normalised 128-bit integer: f = (fhi 2^64 + flo) 2^-128
   uint64_t hi = (uint64_t)R.fhi, lo = R.flo;
   bool neg = R.fhi < 0;

@@ -51,6 +51,18 @@ def ff(x):
     return hi, lo
 
 
+def tf(x):
+    """x as a triple-float h + m + l, each part the binary32 rounding of what
+    the previous parts leave (about 72 significant bits)"""
+    x = mp.mpf(x)
+    h = f32(x)
+    r = x - mp.mpf(h)
+    m = f32(r) if r != 0 else 0.0
+    r -= mp.mpf(m)
+    l = f32(r) if r != 0 else 0.0
+    return h, m, l
+
+
 def fx(v):
     v = float(v)
     if v == 0.0:
@@ -72,6 +84,22 @@ def emit_ff_table(name, vals, comment):
         hi, lo = ff(v)
         emit("  {%s, %s}," % (fx(hi), fx(lo)))
     emit("};")
+
+
+def emit_tf_table(name, vals, comment):
+    emit("// " + comment + ", triple-float {h, m, l, 0}")
+    emit("__device__ __constant__ const float4 %s[%d] = {" % (name, len(vals)))
+    for v in vals:
+        h, m, l = tf(v)
+        emit("  {%s, %s, %s, 0.0f}," % (fx(h), fx(m), fx(l)))
+    emit("};")
+
+
+def emit_tf(name, v, comment=""):
+    h, m, l = tf(v)
+    emit_f(name + "_H", h, comment)
+    emit_f(name + "_M", m)
+    emit_f(name + "_L", l)
 
 
 def emit_f(name, v, comment=""):
@@ -124,9 +152,11 @@ def gen_log():
             lo, hi = (1 + mp.mpf(j) / 16) / 2, (1 + mp.mpf(j + 1) / 16) / 2
         c = 1.0 if j in (0, 15) else bits(2 / (lo + hi), 9, "n")
         c1s.append(c)
+        SLOG_C1S.append(c)
         t_lo, t_hi = lo * c - 1, hi * c - 1
         assert -0.0313 <= t_lo and t_hi <= 0.0626, (j, t_lo, t_hi)
     c2s = [1.0 if i == 0 else bits(1 / (1 + mp.mpf(i) / SLOG_S), 12, "n") for i in range(-8, 8)]
+    SLOG_C2S.extend(c2s)
     emit("// first level: c1 ~ 1/m, 9 bits (1 for the two intervals next to 1)")
     emit("__device__ __constant__ const float SLOG_C1[16] = {%s};" % ", ".join(fx(c) for c in c1s))
     emit("// second level: c2 ~ 1/(1 + i/%d), i = -8..7, 12 bits" % SLOG_S)
@@ -197,7 +227,85 @@ def gen_atan():
     emit()
 
 
+def gen_tf():
+    """Tables and constants of the triple-float accurate step."""
+    emit("// ---- triple-float accurate step ----")
+    emit_tf_table("TFEXP_T1", [mp.power(2, mp.mpf(j) / 16) for j in range(-8, 8)],
+                  "2^(j/16), j = -8..7 (index j + 8)")
+    emit_tf_table("TFEXP_T2", [mp.power(2, mp.mpf(j) / 256) for j in range(-8, 8)],
+                  "2^(j/256), j = -8..7")
+    emit_tf_table("TFEXP_D1", [mp.power(2, mp.mpf(j) / 16) - 1 for j in range(-8, 8)],
+                  "2^(j/16) - 1, j = -8..7")
+    emit_tf_table("TFEXP_D2", [mp.power(2, mp.mpf(j) / 256) - 1 for j in range(-8, 8)],
+                  "2^(j/256) - 1, j = -8..7")
+    ln2 = mp.log(2)
+    C = ln2 / 256
+    c1 = bits(C, 8, "z")
+    c2 = f32(C - c1)
+    c3 = f32(C - c1 - c2)
+    c4 = f32(C - c1 - c2 - c3)
+    emit_f("TFEXP_C4", c4, "fourth part of ln2/256 (after the three of the fast path)")
+    emit_tf("TFEXP_LN2_256", C, "ln2/256")
+    L = 256 * mp.log(10, 2)
+    a = f32(L)
+    b = f32(L - a)
+    c = f32(L - a - b)
+    d = f32(L - a - b - c)
+    emit_f("TFEXP_L10_LL", d, "fourth part of 256 log2(10)")
+    for k in range(3, 8):
+        emit_f("TF_INVFACT%d" % k, f32(1 / mp.factorial(k)), "1/%d!" % k)
+    emit_tf("TF_SIXTH", mp.mpf(1) / 6, "1/6")
+    emit_tf("TF_THIRD", mp.mpf(1) / 3, "1/3")
+    h, l = ff(mp.mpf(1) / 120)
+    emit_f("TF_INV120_H", h, "1/120 hi")
+    emit_f("TF_INV120_L", l, "1/120 lo")
+    h, l = ff(mp.mpf(1) / 24)
+    emit_f("TF_INV24_H", h, "1/24 hi")
+    emit_f("TF_INV24_L", l, "1/24 lo")
+    h, l = ff(mp.mpf(1) / 5)
+    emit_f("TF_FIFTH_H", h, "1/5 hi")
+    emit_f("TF_FIFTH_L", l, "1/5 lo")
+    for k in range(5, 10):
+        emit_f("TF_RECIP%d" % k, f32(mp.mpf(1) / k), "1/%d" % k)
+    # log: -log c1, -log c2 of the split reduction, ln 2 and log10(2) in four
+    # parts (the first 16 bits wide: e times it is exact)
+    c1s, c2s = SLOG_C1S, SLOG_C2S
+    emit_tf_table("TFLOG_L1", [-mp.log(c) for c in c1s], "-log(c1)")
+    emit_tf_table("TFLOG_L2", [-mp.log(c) for c in c2s], "-log(c2)")
+    for name, v in (("TFLOG_LN2", ln2), ("TFLOG_LG2", mp.log(2, 10))):
+        a = bits(v, 16, "n")
+        b = f32(v - a)
+        c = f32(v - a - b)
+        d = f32(v - a - b - c)
+        emit_f(name + "_H", a, "16 bits (e times it is exact)")
+        emit_f(name + "_M", b)
+        emit_f(name + "_L", c)
+        emit_f(name + "_LL", d)
+    emit_tf("TFLOG_INV_LN2", 1 / ln2, "1/ln2")
+    emit_tf("TFLOG_INV_LN10", 1 / mp.log(10), "1/ln10")
+    # trig
+    emit_tf_table("TFTRIG_S", [mp.sin(mp.pi * j / 32) for j in range(16)], "sin(j pi/32), j = 0..15")
+    emit_tf_table("TFTRIG_C", [mp.cos(mp.pi * j / 32) for j in range(16)], "cos(j pi/32), j = 0..15")
+    emit_tf("TFTRIG_PI32", mp.pi / 32, "pi/32")
+    for k in (7, 9, 11, 13):
+        emit_f("TFTRIG_S%d" % k, f32(mp.mpf((-1) ** ((k - 1) // 2)) / mp.factorial(k)),
+               "(-1)^((k-1)/2)/%d!" % k)
+    for k in (6, 8, 10, 12):
+        emit_f("TFTRIG_C%d" % k, f32(mp.mpf((-1) ** (k // 2)) / mp.factorial(k)),
+               "(-1)^(k/2)/%d!" % k)
+    # inverse trig
+    emit_tf_table("TFATAN_A", [mp.atan(mp.mpf(j) / 16) for j in range(16)], "atan(j/16)")
+    emit_tf_table("TFATAN_B", [mp.pi / 2 - mp.atan(mp.mpf(j) / 16) for j in range(16)],
+                  "pi/2 - atan(j/16)")
+    emit_tf("TFATAN_PI", mp.pi, "pi")
+    for k in (7, 9, 11, 13):
+        emit_f("TFATAN_P%d" % k, f32(mp.mpf((-1) ** ((k - 1) // 2)) / k), "(-1)^((k-1)/2)/%d" % k)
+    emit()
+
+
 SLOG_S = 112
+SLOG_C1S = []
+SLOG_C2S = []
 
 
 def main():
@@ -210,6 +318,7 @@ def main():
     gen_log()
     gen_trig()
     gen_atan()
+    gen_tf()
     with open(OUT, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("wrote", OUT)

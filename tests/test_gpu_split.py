@@ -1,6 +1,8 @@
-"""The binary32-only (split, float-float) implementation: bit-exact parity with
-the oracle, and exhaustive agreement of its fast path with the accurate path
-over all 2^32 inputs (needs a GPU)."""
+"""The binary32-only (split) implementation: float-float fast path,
+triple-float accurate step, no binary64 operation.  Bit-exact parity with the
+oracle, exhaustive agreement of its fast path with its accurate step, and of
+its accurate step (forced on every element) with the binary64-internal
+implementation, over all 2^32 inputs (needs a GPU)."""
 import numpy as np
 import pytest
 
@@ -10,7 +12,7 @@ torch = pytest.importorskip("torch")
 
 from paper_2605_15547_amd import crmath, inputs  # noqa: E402
 
-from test_gpu_parity import assert_same, gpu_eval  # noqa: E402
+from test_gpu_parity import _edge_inputs, assert_same, gpu_eval  # noqa: E402
 
 SPLIT = crmath.IMPL_SPLIT_F32
 F32 = crmath.FUNCS32
@@ -60,6 +62,26 @@ def test_split_special_inputs(oracle, func):
                          np.nextafter(ks, np.float32(np.inf)),
                          np.nextafter(ks, np.float32(-np.inf))])
     assert_same(func, sp, gpu_eval(func, sp, impl=SPLIT), oracle.evaluate(func, sp))
+
+
+@pytest.mark.parametrize("func", [f for f in F32 if f != "rsqrtf"])
+def test_split_triple_float_step_matches_oracle(oracle, func):
+    """Every element through the triple-float step: workload, hard set,
+    regime edges, raw encodings (specials, subnormals), tiny arguments."""
+    _need(func)
+    st = inputs.Stream(31_000 + crmath.FUNC_ID[func])
+    tiny = np.ldexp(np.float32(1) + st.uniform(512).astype(np.float32),
+                    -(12 + st.below(512, 130)).astype(np.int32)).astype(np.float32)
+    parts = [inputs.workload_f32(func, 30_011, seed=31_100 + crmath.FUNC_ID[func]),
+             inputs.hard_set(func), _edge_inputs(func), inputs.f32_bits(st.u32(8192)),
+             tiny, -tiny]
+    x = np.ascontiguousarray(np.concatenate([p for p in parts if p is not None]),
+                             dtype=np.float32)
+    crmath.stats_reset()
+    got = gpu_eval(func, x, impl=SPLIT, flags=crmath.FLAG_FORCE_FALLBACK)
+    stt = crmath.stats_read()
+    assert_same(func, x, got, oracle.evaluate(func, x))
+    assert stt["escapes"] == 0, stt
 
 
 def test_split_expf_correctness_set(oracle):
@@ -142,3 +164,38 @@ def test_split_rsqrtf_exhaustive_matches_binary64_decision():
         del a, b, bad, x
     torch.cuda.synchronize()
     assert total_bad == 0, (total_bad, first)
+
+
+@pytest.mark.parametrize("func", [f for f in F32 if f != "rsqrtf"])
+def test_split_triple_float_step_exhaustive_matches_binary64_path(func):
+    """Every binary32 encoding through the triple-float step (forced on every
+    element) gives the bits of the binary64-internal implementation, with no
+    escape: the binary32-only accurate step decides every input on its own."""
+    _need(func)
+    sp = crmath._stream_ptr(None)
+    crmath.stats_reset()
+    total_bad, first = 0, None
+    for c in range(1 << 32 >> 28):
+        xi = torch.arange(c * CHUNK, (c + 1) * CHUNK, dtype=torch.int64, device="cuda")
+        x = xi.to(torch.int32).view(torch.float32)
+        del xi
+        n = x.numel()
+        nout = 2 * n if func == "sincosf" else n
+        a = torch.empty(nout, dtype=torch.float32, device="cuda")
+        b = torch.empty(nout, dtype=torch.float32, device="cuda")
+        crmath.eval_ptr(func, x.data_ptr(), a.data_ptr(), n, SPLIT, crmath.FLAG_FORCE_FALLBACK, sp)
+        st = crmath.stats_read()
+        assert st["escapes"] == 0, (func, hex(c * CHUNK), st)
+        crmath.eval_ptr(func, x.data_ptr(), b.data_ptr(), n, crmath.IMPL_F64_INTERNAL, 0, sp)
+        # NaN results: compare as NaN (payloads are checked by the parity tests)
+        av, bv = a.view(torch.int32), b.view(torch.int32)
+        bad = (av != bv) & ~(torch.isnan(a) & torch.isnan(b))
+        nb = int(bad.sum().item())
+        if nb and first is None:
+            i = int(torch.nonzero(bad)[0].item())
+            first = (hex(c * CHUNK + i % CHUNK), hex(int(av[i].item()) & 0xffffffff),
+                     hex(int(bv[i].item()) & 0xffffffff))
+        total_bad += nb
+        del a, b, av, bv, bad, x
+    torch.cuda.synchronize()
+    assert total_bad == 0, (func, total_bad, first)
