@@ -94,5 +94,11 @@ __device__ __forceinline__ double pow2i(int m) {
 
 __device__ __forceinline__ uint32_t f32_bits(float x) { return __float_as_uint(x); }
 __device__ __forceinline__ float bits_f32(uint32_t b) { return __uint_as_float(b); }
+// x quieted (payload and sign kept) when x is a NaN, else v -- an integer
+// select: as a float conditional the compiler branches around the bit operation
+__device__ __forceinline__ float nan_or(float x, float v) {
+  const uint32_t q = f32_bits(x) | 0x00400000u;
+  return bits_f32(x != x ? q : f32_bits(v));
+}
 
 }  // namespace cr

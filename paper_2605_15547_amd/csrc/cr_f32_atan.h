@@ -65,7 +65,7 @@ __device__ __forceinline__ bool atan_special(float xf, int kind, float& res) {
   const bool zero = kind != ATANK_ACOS && xf == 0.0f;  // atan(+-0) = asin(+-0) = +-0
   const bool one = kind == ATANK_ACOS && xf == 1.0f;
   float v = zero ? xf : (one ? 0.0f : bits_f32(0x7fc00000u));
-  res = nan ? bits_f32(f32_bits(xf) | 0x00400000u) : v;
+  res = nan_or(xf, v);
   return nan | dom | zero | one;
 }
 
@@ -86,12 +86,11 @@ __device__ __forceinline__ float atan_fast(float xf, const AtanTab& tb, bool& ok
       if (xf < 0.0f) yh = -yh;
     } else {
       atan_ratio_fast(s, a, tb, hi, lo);
-      if (xf < 0.0f) {  // pi - atan(s/|x|)
-        dd p = fast_two_sum(PI_HI, -hi);
-        yh = p.hi + (p.lo + (PI_LO - lo));
-      } else {
-        yh = hi + lo;
-      }
+      // pi - atan(s/|x|) for x < 0, atan(s/x) otherwise, as selects (an
+      // if/else compiles to branches that a mixed-sign wave runs both sides of)
+      const bool neg = xf < 0.0f;
+      dd p = fast_two_sum(neg ? PI_HI : 0.0, neg ? -hi : hi);
+      yh = p.hi + (p.lo + ((neg ? PI_LO : 0.0) + (neg ? -lo : lo)));
     }
   }
   float res = round_f32_fast<ATAN_LOG2E>(yh, ok);

@@ -157,7 +157,7 @@ __device__ __forceinline__ bool exp_special(float xf, float& res) {
   const bool tie = K == EXPK_2 && xf == -150.0f;
   const bool zero = K == EXPK_EM1 && xf == 0.0f;
   float v = zero ? xf : 0.0f;
-  res = nan ? bits_f32(f32_bits(xf) | 0x00400000u) : v;
+  res = nan_or(xf, v);
   return nan | tie | zero;
 }
 

@@ -43,7 +43,7 @@ constexpr int HYP_LOG2E = 5;
 __device__ __forceinline__ bool hyp_special(float xf, int kind, float& res) {
   const bool nan = xf != xf;
   const bool zero = kind != HYPK_COSH && xf == 0.0f;
-  res = nan ? bits_f32(f32_bits(xf) | 0x00400000u) : xf;
+  res = nan_or(xf, xf);
   return nan | zero;
 }
 

@@ -152,7 +152,7 @@ __device__ __forceinline__ bool log_special(float xf, float& res) {
   const bool inf = xf == INFINITY;
   float v = inf ? INFINITY : (xf == lim ? -INFINITY : bits_f32(0x7fc00000u));
   v = zero1p ? xf : v;
-  res = nan ? bits_f32(f32_bits(xf) | 0x00400000u) : v;
+  res = nan_or(xf, v);
   return nan | zero1p | dom | inf;
 }
 

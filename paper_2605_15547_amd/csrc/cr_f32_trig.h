@@ -143,7 +143,7 @@ __device__ __forceinline__ bool trig_special(float xf, float& res, int kind) {
   const bool inf = (f32_bits(xf) & 0x7fffffffu) == 0x7f800000u;
   const bool zero = xf == 0.0f;
   float v = zero ? (kind == TRIGK_COS ? 1.0f : xf) : bits_f32(0x7fc00000u);  // sin, tan keep -0
-  res = nan ? bits_f32(f32_bits(xf) | 0x00400000u) : v;
+  res = nan_or(xf, v);
   return nan | inf | zero;
 }
 

@@ -100,10 +100,9 @@ __device__ __forceinline__ float satan_fast(float xf, const SAtanTab& tb, bool& 
       if (neg) y = {-y.hi, -y.lo};
     } else {
       y = satan_ratio(s, ff{ac, 0.0f}, tb);
-      if (neg) {  // pi - atan(s/|x|)
-        ff d = ff_two_sum(SATAN_PI_H, -y.hi);
-        y = {d.hi, d.lo + (SATAN_PI_L - y.lo)};
-      }
+      // pi - atan(s/|x|) for x < 0, as selects (no branch)
+      ff d = ff_two_sum(neg ? SATAN_PI_H : 0.0f, neg ? -y.hi : y.hi);
+      y = {d.hi, d.lo + ((neg ? SATAN_PI_L : 0.0f) + (neg ? -y.lo : y.lo))};
     }
   }
   float res = round_split(y.hi, y.lo, fabsf(y.hi) * 0x1p-42f, ok);
