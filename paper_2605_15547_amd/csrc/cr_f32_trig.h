@@ -9,8 +9,10 @@
 //   with g_i the bits of 2/pi.  Bits with i <= E - 2 only add multiples of 64
 //   to N, so a 160-bit window W of 2/pi starting at bit E - 1 suffices:
 //   N = M W 2^-154 (mod 64), truncation error < 2^24 2^-154 = 2^-130.
-//   The window is read from a 10-word table (a zero word, then 288 bits of
-//   2/pi) with funnel shifts; the binary point of P = M W is always bit 154.
+//   The window is read from an 11-word table (two zero words, then 288 bits
+//   of 2/pi) with funnel shifts; the binary point of P = M W is always bit
+//   154.  The zero words let the window start before the binary point, so the
+//   reduction is also right for small arguments (down to 2^-37).
 //
 //   k = nearest(N), q = k mod 64, f = N - k in [-1/2, 1/2) (64 fraction bits
 //   for the fast path, 128 for the accurate path), r = f pi/32, |r| <= pi/64.
@@ -31,12 +33,12 @@ enum { TRIGK_SIN = 0, TRIGK_COS = 1, TRIGK_TAN = 2, TRIGK_SINCOS = 3 };
 
 struct TrigTab {
   double4 sc[16];
-  unsigned w[10];
+  unsigned w[11];
 };
 
 __device__ __forceinline__ void trig_tab_load(TrigTab& t, int tid) {
   if (tid < 16) t.sc[tid] = SINCOS_T[tid];
-  if (tid < 10) t.w[tid] = TWO_OVER_PI_W[tid];
+  if (tid < 11) t.w[tid] = TWO_OVER_PI_W[tid];
 }
 
 struct Reduced {
@@ -45,23 +47,36 @@ struct Reduced {
   unsigned long long flo;
 };
 
-// Payne-Hanek reduction of |x| (ax = its encoding), |x| >= pi/64 and finite;
+// The 32-bit words of the window W that starts at bit sp of the zero-prefixed
+// bit string of 2/pi: word k is bits [sp + 32k, sp + 32k + 32), the funnel
+// shift of w[b + k] and w[b + k + 1] right by c, with b = ceil(sp / 32) - 1 and
+// c = -sp mod 32 (c = 0 when sp is a multiple of 32: word k is then
+// w[b + k + 1] itself), so that the shift count stays in [0, 31].
+struct Window {
+  int b;
+  unsigned c;
+};
+__device__ __forceinline__ Window window_of(int sp) {
+  return {((sp + 31) >> 5) - 1, (unsigned)(-sp) & 31u};
+}
+__device__ __forceinline__ uint32_t window_word(uint32_t hi, uint32_t lo, unsigned c) {
+  return (uint32_t)((((uint64_t)hi << 32) | lo) >> c);
+}
+
+// Payne-Hanek reduction of |x| (ax = its encoding), 2^-37 <= |x| finite;
 // other encodings are clamped to in-range table indices (their result is
 // discarded by the caller).
 __device__ __forceinline__ Reduced payne_hanek(uint32_t ax, const unsigned* w) {
   int E = (int)(ax >> 23) - 150;
-  E = E < -28 ? -28 : (E > 105 ? 105 : E);
+  E = E < -60 ? -60 : (E > 105 ? 105 : E);
   uint32_t M = (ax & 0x007fffffu) | 0x00800000u;
-  int sp = E - 2 + 32;  // window start in the zero-prefixed bit string: [2, 135]
-  int wi = sp >> 5, sh = 32 - (sp & 31);
-  uint32_t t0 = w[wi], t1 = w[wi + 1], t2 = w[wi + 2], t3 = w[wi + 3], t4 = w[wi + 4],
-           t5 = w[wi + 5];
-  // W_k = 32 bits of the window (funnel shift; sh = 32 gives the word itself)
-  uint32_t W0 = (uint32_t)((((uint64_t)t0 << 32) | t1) >> sh);
-  uint32_t W1 = (uint32_t)((((uint64_t)t1 << 32) | t2) >> sh);
-  uint32_t W2 = (uint32_t)((((uint64_t)t2 << 32) | t3) >> sh);
-  uint32_t W3 = (uint32_t)((((uint64_t)t3 << 32) | t4) >> sh);
-  uint32_t W4 = (uint32_t)((((uint64_t)t4 << 32) | t5) >> sh);
+  const Window win = window_of(E - 2 + 64);  // window start: [2, 167]
+  const unsigned* t = w + win.b;             // words b .. b + 5 <= 10
+  uint32_t W0 = window_word(t[0], t[1], win.c);
+  uint32_t W1 = window_word(t[1], t[2], win.c);
+  uint32_t W2 = window_word(t[2], t[3], win.c);
+  uint32_t W3 = window_word(t[3], t[4], win.c);
+  uint32_t W4 = window_word(t[4], t[5], win.c);
   // P = M W, least significant word first (each step is one 32x32+64 multiply-add)
   uint64_t a = (uint64_t)M * W4;
   uint32_t p0 = (uint32_t)a;
@@ -91,14 +106,13 @@ __device__ __forceinline__ Reduced payne_hanek(uint32_t ax, const unsigned* w) {
 // 2^-64 (the high word R.fhi only; R.flo is not formed).
 __device__ __forceinline__ Reduced payne_hanek_fast(uint32_t ax, const unsigned* w) {
   int E = (int)(ax >> 23) - 150;
-  E = E < -28 ? -28 : (E > 105 ? 105 : E);
+  E = E < -60 ? -60 : (E > 105 ? 105 : E);
   uint32_t M = (ax & 0x007fffffu) | 0x00800000u;
-  int sp = E - 2 + 32;
-  int wi = sp >> 5, sh = 32 - (sp & 31);
-  uint32_t t0 = w[wi], t1 = w[wi + 1], t2 = w[wi + 2], t3 = w[wi + 3];
-  uint32_t W0 = (uint32_t)((((uint64_t)t0 << 32) | t1) >> sh);
-  uint32_t W1 = (uint32_t)((((uint64_t)t1 << 32) | t2) >> sh);
-  uint32_t W2 = (uint32_t)((((uint64_t)t2 << 32) | t3) >> sh);
+  const Window win = window_of(E - 2 + 64);
+  const unsigned* t = w + win.b;
+  uint32_t W0 = window_word(t[0], t[1], win.c);
+  uint32_t W1 = window_word(t[1], t[2], win.c);
+  uint32_t W2 = window_word(t[2], t[3], win.c);
   uint64_t a = (uint64_t)M * W2;
   uint32_t p2 = (uint32_t)a;
   a = (uint64_t)M * W1 + (a >> 32);
@@ -163,15 +177,17 @@ __device__ __forceinline__ bool trig_special_fast(float xf, float& res, int kind
   return __builtin_amdgcn_class(xf, 0x207) | (fabsf(xf) < 0x1p-12f);
 }
 
-// Fast path: binary64 sin and cos of x with absolute error bounds.
+// Fast path: binary64 sin and cos of |x| up to the quadrant's signs, with
+// absolute error bounds: sin |x| is s with its sign flipped by the mask ss
+// (bit 63), cos |x| is c flipped by sc.
 struct TrigFast {
   double s, c, es, ec;  // values and error bounds
+  long long ss, sc;     // sign masks
 };
 
 __device__ __forceinline__ TrigFast trig_fast_core(float xf, const TrigTab& tb) {
   uint32_t ax = f32_bits(xf) & 0x7fffffffu;
   double axd = (double)bits_f32(ax);
-  bool small = axd < PI64;
   double r;
   int q;
   // The one branch of the method is on the size of the argument (the paper
@@ -181,9 +197,11 @@ __device__ __forceinline__ TrigFast trig_fast_core(float xf, const TrigTab& tb) 
   // - k C3 with C1 on 26 bits (k C1 exact, and |x| - k C1 exact: a multiple
   // of 2^-29 below 2^-4) and k C2 as an exact product: r within
   // 2^-53 |r| + 2^-105 of |x| - k pi/32 (the final addition's rounding and
-  // the terms below 2^-57), inside the bound below.  The branch is
-  // wave-uniform, so it costs no divergence; the result is certified by the
-  // same test either way, so it does not depend on which branch runs.
+  // the terms below 2^-57), inside the bound below; for |x| < pi/64, k = 0
+  // and r = |x| exactly.  The branch is wave-uniform, so it costs no
+  // divergence; the result is certified by the same test either way, so it
+  // does not depend on which branch runs.  Payne-Hanek is right down to
+  // |x| = 2^-37; smaller arguments are special cases (|x| < 2^-12).
   if (__all(ax < 0x4b000000u)) {
     const double kd = rint(axd * INV_PI32);
     const double r1 = fma(-kd, PI32_CW1, axd);
@@ -195,38 +213,55 @@ __device__ __forceinline__ TrigFast trig_fast_core(float xf, const TrigTab& tb) 
     Reduced R = payne_hanek_fast(ax, tb.w);
     // f = fhi 2^-64 (the reduction leaves it low by less than 2^-64; the bits
     // below are not formed), as the exact sum of its signed high and
-    // unsigned low 32-bit halves
-    double fh = (double)(int)(R.fhi >> 32) * 0x1p-32;
-    double fl = (double)(uint32_t)R.fhi * 0x1p-64;
-    r = fma(fh, PI32_HI, fma(fh, PI32_MID, fl * PI32_HI));
+    // unsigned low 32-bit halves; their weights 2^-32 and 2^-64 are folded
+    // into the constants (exact scalings)
+    double fh = (double)(int)(R.fhi >> 32);
+    double fl = (double)(uint32_t)R.fhi;
+    r = fma(fh, PI32_HI * 0x1p-32, fma(fh, PI32_MID * 0x1p-32, fl * (PI32_HI * 0x1p-64)));
     q = R.q;
-  }
-  if (small) {
-    r = axd;
-    q = 0;
   }
   double r2 = r * r;
   double ps = fma(fma(SIN_S2[2], r2, SIN_S2[1]), r2, SIN_S2[0]);
   double pc = fma(fma(COS_C2[2], r2, COS_C2[1]), r2, COS_C2[0]);
   double sr = fma(r * r2, ps, r);  // sin r
   double cm1 = r2 * pc;            // cos r - 1
-  SinCosTheta th = theta_of(q, tb);
+  // theta = q pi/32 = quad pi/2 + j pi/32, with T1, T2 = sin, cos of j pi/32
+  // (the high parts of table row j) swapped in odd quadrants: an offset of
+  // the two reads, from bit 4 of q.  Then
+  //   sin x = +-(T1 + T1 (cos r - 1) + T2 sr'),
+  //   cos x = +-(T2 + T2 (cos r - 1) - T1 sr'),
+  // with sr' = sin r negated in odd quadrants and the outer signs given by
+  // bit 5 of q (sin) and bit 4 xor bit 5 (cos).
+  const double* row = reinterpret_cast<const double*>(&tb.sc[q & 15]);
+  const int sw = (q >> 3) & 2;
+  const double T1 = row[sw], T2 = row[sw ^ 2];
+  const double srq = __longlong_as_double(__double_as_longlong(sr) ^ ((long long)(q & 16) << 59));
   TrigFast o;
-  // the table's high parts only (sin and cos of j pi/32 to 2^-54)
-  o.s = th.sh + fma(th.sh, cm1, th.ch * sr);
-  o.c = th.ch + fma(th.ch, cm1, -(th.sh * sr));
+  o.s = T1 + fma(T1, cm1, T2 * srq);
+  o.c = T2 + fma(T2, cm1, -(T1 * srq));
+  o.ss = (long long)(q & 32) << 58;
+  o.sc = (long long)((q ^ (q << 1)) & 32) << 58;
   // Error bounds, absolute: r within 2^-52 |r| + 2^-66.35 (reduction, f to
-  // 2^-63 in units of N; exact when |x| < pi/64); the degree-2 corrections
-  // within 2^-50.1 (cos) and 2^-57.6 (sin) -- the bound tests re-derive both;
-  // the table entries within 2^-54 each; three roundings of terms below 0.05
-  // and the final one of y.  With |sin x|, |cos x| >= 0.049 unless j = 0 this
-  // is below 2^-49.95 absolute, i.e. 2^-45.6 |y|.  For j = 0 the table terms
-  // are exactly 0 and +-1 and y is +-sin r (within 2^-57.6 + 2^-51.9 |y| +
-  // 2^-66.35) or +-cos r (within 2^-50.1, |y| > 0.99).  Bound used:
-  // 2^-45 |y| + 2^-57.
+  // 2^-63 in units of N; exact when the Cody-Waite branch has k = 0); the
+  // degree-2 corrections within 2^-50.1 (cos) and 2^-57.6 (sin) -- the bound
+  // tests re-derive both; the table entries within 2^-54 each; three
+  // roundings of terms below 0.05 and the final one of y.  With |sin x|,
+  // |cos x| >= 0.049 unless j = 0 this is below 2^-49.95 absolute, i.e.
+  // 2^-45.6 |y|.  For j = 0 the table terms are exactly 0 and 1 and y is
+  // +-sin r (within 2^-57.6 + 2^-51.9 |y| + 2^-66.35) or +-cos r (within
+  // 2^-50.1, |y| > 0.99).  Bound used: 2^-45 |y| + 2^-57.
   o.es = fma(fabs(o.s), 0x1p-45, 0x1p-57);
   o.ec = fma(fabs(o.c), 0x1p-45, 0x1p-57);
   return o;
+}
+
+// v with its sign flipped where the mask m has bit 63 set
+__device__ __forceinline__ double flip(double v, long long m) {
+  return __longlong_as_double(__double_as_longlong(v) ^ m);
+}
+// bit 63 set when x is negative
+__device__ __forceinline__ long long sign_mask(float xf) {
+  return (long long)(f32_bits(xf) >> 31) << 63;
 }
 
 // The rounding test of the sin and cos fast paths, read off the bits of yh:
@@ -365,19 +400,19 @@ __device__ __noinline__ AccResult2 sincos_accurate(float xf, const TrigTab& tb) 
 template <int KIND>
 __device__ __forceinline__ float trig_fast(float xf, const TrigTab& tb, bool& ok) {
   TrigFast F = trig_fast_core(xf, tb);
-  bool neg = xf < 0.0f;
+  const long long xs = sign_mask(xf);
   float res;
   if (KIND == TRIGK_COS) {
-    res = round_trig_fast(F.c, ok);
+    res = round_trig_fast(flip(F.c, F.sc), ok);
   } else if (KIND == TRIGK_SIN) {
-    res = round_trig_fast(neg ? -F.s : F.s, ok);
+    res = round_trig_fast(flip(F.s, F.ss ^ xs), ok);
   } else {
     double t = F.s / F.c;
     // relative error of the quotient plus the absolute errors of s and c
     // magnified by 1/|c|: |dt| <= |t| 2^-52 + (es + |t| ec) / |c|
     double ic = __builtin_amdgcn_rcp(fabs(F.c));
     double e = fma(fabs(t), 0x1p-50, (F.es + fabs(t) * F.ec) * ic * 2.0);
-    res = round_f32_fast_abs(neg ? -t : t, e, ok);
+    res = round_f32_fast_abs(flip(t, F.ss ^ F.sc ^ xs), e, ok);
   }
   float sp;
   if (trig_special_fast(xf, sp, KIND)) {
@@ -391,8 +426,8 @@ __device__ __forceinline__ float trig_fast(float xf, const TrigTab& tb, bool& ok
 __device__ __forceinline__ float sincos_fast(float xf, const TrigTab& tb, float& c, bool& ok) {
   TrigFast F = trig_fast_core(xf, tb);
   bool ok1, ok2;
-  float s = round_trig_fast(xf < 0.0f ? -F.s : F.s, ok1);
-  c = round_trig_fast(F.c, ok2);
+  float s = round_trig_fast(flip(F.s, F.ss ^ sign_mask(xf)), ok1);
+  c = round_trig_fast(flip(F.c, F.sc), ok2);
   ok = ok1 && ok2;
   float sp;
   if (trig_special_fast(xf, sp, TRIGK_SIN)) {

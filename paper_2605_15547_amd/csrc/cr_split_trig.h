@@ -27,12 +27,12 @@ namespace cr {
 
 struct STrigTab {
   float4 sc[16];
-  unsigned w[10];  // the words of 2/pi of the Payne-Hanek reduction
+  unsigned w[11];  // the words of 2/pi of the Payne-Hanek reduction
 };
 
 __device__ __forceinline__ void strig_tab_load(STrigTab& t, int tid) {
   if (tid < 16) t.sc[tid] = STRIG_T[tid];
-  if (tid < 10) t.w[tid] = TWO_OVER_PI_W[tid];
+  if (tid < 11) t.w[tid] = TWO_OVER_PI_W[tid];
 }
 
 // float-float product a b (|result| error ~2^-47 relative)

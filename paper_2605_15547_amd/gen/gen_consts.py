@@ -291,15 +291,16 @@ def gen_log():
 # =================================================================== trig family
 def gen_trig():
     emit("// ---- trigonometric family (sinf, cosf, sincosf, tanf) ----")
-    # 2/pi = sum g_i 2^-i; word k (k >= 1) holds bits 32(k-1)+1 .. 32k; word 0 is
-    # zero so that windows may start before the binary point
-    words = [0]
+    # 2/pi = sum g_i 2^-i; word k (k >= 2) holds bits 32(k-2)+1 .. 32(k-1); words
+    # 0 and 1 are zero so that windows may start up to 64 bits before the binary
+    # point (arguments down to 2^-37 reduce correctly)
+    words = [0, 0]
     with mp.workprec(800):  # 288 table bits need far more than the default precision
         two_over_pi = 2 / mp.pi
         for k in range(1, 10):
             words.append(int(mp.floor(two_over_pi * mp.mpf(2) ** (32 * k))) & 0xFFFFFFFF)
-    emit("// bits of 2/pi: word k (k >= 1) = bits 32(k-1)+1 .. 32k; word 0 = 0")
-    emit("__device__ __constant__ const unsigned TWO_OVER_PI_W[10] = {%s};"
+    emit("// bits of 2/pi: word k (k >= 2) = bits 32(k-2)+1 .. 32(k-1); words 0, 1 = 0")
+    emit("__device__ __constant__ const unsigned TWO_OVER_PI_W[11] = {%s};"
          % ", ".join("0x%08xu" % w for w in words))
     h, m1, l = td(mp.pi / 32)
     emit_const("PI32_HI", h, "pi/32")
