@@ -59,8 +59,12 @@ struct Window {
 __device__ __forceinline__ Window window_of(int sp) {
   return {((sp + 31) >> 5) - 1, (unsigned)(-sp) & 31u};
 }
+// ((hi:lo) >> c) mod 2^32 for c in [0, 31]: one funnel shift
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, unsigned c) {
+  return __builtin_amdgcn_alignbit(hi, lo, c);
+}
 __device__ __forceinline__ uint32_t window_word(uint32_t hi, uint32_t lo, unsigned c) {
-  return (uint32_t)((((uint64_t)hi << 32) | lo) >> c);
+  return funnel(hi, lo, c);
 }
 
 // Payne-Hanek reduction of |x| (ax = its encoding), 2^-37 <= |x| finite;
@@ -88,13 +92,12 @@ __device__ __forceinline__ Reduced payne_hanek(uint32_t ax, const unsigned* w) {
   uint32_t p3 = (uint32_t)a;
   a = (uint64_t)M * W0 + (a >> 32);
   uint32_t p4 = (uint32_t)a;
-  // integer bits 154..159 = p4[31:26]; fraction bits 153..26
-  uint64_t F = ((uint64_t)(p4 & 0x03ffffffu) << 38) | ((uint64_t)p3 << 6) | (p2 >> 26);
-  uint64_t Fl = ((uint64_t)(p2 & 0x03ffffffu) << 38) | ((uint64_t)p1 << 6) | (p0 >> 26);
+  // integer bits 154..159 = p4[31:26]; fraction bits 153..26, by 32-bit words
+  // the funnel shifts of (p4:p3), (p3:p2), (p2:p1), (p1:p0) right by 26
   Reduced R;
-  R.q = (int)(((p4 >> 26) + (uint32_t)(F >> 63)) & 63);  // round to nearest
-  R.fhi = (long long)F;                                   // f - 1 when f >= 1/2
-  R.flo = Fl;
+  R.q = (int)((((p4 >> 25) + 1) >> 1) & 63);  // round to nearest: + fraction bit 153
+  R.fhi = (long long)(((uint64_t)funnel(p4, p3, 26) << 32) | funnel(p3, p2, 26));  // f - 1 when f >= 1/2
+  R.flo = ((uint64_t)funnel(p2, p1, 26) << 32) | funnel(p1, p0, 26);
   return R;
 }
 
@@ -119,10 +122,9 @@ __device__ __forceinline__ Reduced payne_hanek_fast(uint32_t ax, const unsigned*
   uint32_t p3 = (uint32_t)a;
   a = (uint64_t)M * W0 + (a >> 32);
   uint32_t p4 = (uint32_t)a;
-  uint64_t F = ((uint64_t)(p4 & 0x03ffffffu) << 38) | ((uint64_t)p3 << 6) | (p2 >> 26);
   Reduced R;
-  R.q = (int)(((p4 >> 26) + (uint32_t)(F >> 63)) & 63);
-  R.fhi = (long long)F;
+  R.q = (int)((((p4 >> 25) + 1) >> 1) & 63);
+  R.fhi = (long long)(((uint64_t)funnel(p4, p3, 26) << 32) | funnel(p3, p2, 26));
   R.flo = 0;
   return R;
 }
@@ -177,12 +179,18 @@ __device__ __forceinline__ bool trig_special_fast(float xf, float& res, int kind
   return __builtin_amdgcn_class(xf, 0x207) | (fabsf(xf) < 0x1p-12f);
 }
 
+// v with its sign flipped where the mask m has bit 31 set (one operation on
+// the high word)
+__device__ __forceinline__ double flip(double v, uint32_t m) {
+  return __hiloint2double(__double2hiint(v) ^ (int)(m & 0x80000000u), __double2loint(v));
+}
+
 // Fast path: binary64 sin and cos of |x| up to the quadrant's signs, with
 // absolute error bounds: sin |x| is s with its sign flipped by the mask ss
-// (bit 63), cos |x| is c flipped by sc.
+// (bit 31), cos |x| is c flipped by sc.
 struct TrigFast {
   double s, c, es, ec;  // values and error bounds
-  long long ss, sc;     // sign masks
+  uint32_t ss, sc;      // sign masks
 };
 
 __device__ __forceinline__ TrigFast trig_fast_core(float xf, const TrigTab& tb) {
@@ -235,12 +243,13 @@ __device__ __forceinline__ TrigFast trig_fast_core(float xf, const TrigTab& tb) 
   const double* row = reinterpret_cast<const double*>(&tb.sc[q & 15]);
   const int sw = (q >> 3) & 2;
   const double T1 = row[sw], T2 = row[sw ^ 2];
-  const double srq = __longlong_as_double(__double_as_longlong(sr) ^ ((long long)(q & 16) << 59));
+  const uint32_t q32 = (uint32_t)q;
+  const double srq = flip(sr, q32 << 27);
   TrigFast o;
   o.s = T1 + fma(T1, cm1, T2 * srq);
   o.c = T2 + fma(T2, cm1, -(T1 * srq));
-  o.ss = (long long)(q & 32) << 58;
-  o.sc = (long long)((q ^ (q << 1)) & 32) << 58;
+  o.ss = q32 << 26;
+  o.sc = (q32 ^ (q32 << 1)) << 26;
   // Error bounds, absolute: r within 2^-52 |r| + 2^-66.35 (reduction, f to
   // 2^-63 in units of N; exact when the Cody-Waite branch has k = 0); the
   // degree-2 corrections within 2^-50.1 (cos) and 2^-57.6 (sin) -- the bound
@@ -255,14 +264,8 @@ __device__ __forceinline__ TrigFast trig_fast_core(float xf, const TrigTab& tb) 
   return o;
 }
 
-// v with its sign flipped where the mask m has bit 63 set
-__device__ __forceinline__ double flip(double v, long long m) {
-  return __longlong_as_double(__double_as_longlong(v) ^ m);
-}
-// bit 63 set when x is negative
-__device__ __forceinline__ long long sign_mask(float xf) {
-  return (long long)(f32_bits(xf) >> 31) << 63;
-}
+// bit 31 set when x is negative
+__device__ __forceinline__ uint32_t sign_mask(float xf) { return f32_bits(xf); }
 
 // The rounding test of the sin and cos fast paths, read off the bits of yh:
 // for |yh| >= 2^-12 the bound above is below 2^-44 |yh| (the absolute term is
@@ -400,18 +403,22 @@ __device__ __noinline__ AccResult2 sincos_accurate(float xf, const TrigTab& tb) 
 template <int KIND>
 __device__ __forceinline__ float trig_fast(float xf, const TrigTab& tb, bool& ok) {
   TrigFast F = trig_fast_core(xf, tb);
-  const long long xs = sign_mask(xf);
+  const uint32_t xs = sign_mask(xf);
   float res;
   if (KIND == TRIGK_COS) {
     res = round_trig_fast(flip(F.c, F.sc), ok);
   } else if (KIND == TRIGK_SIN) {
     res = round_trig_fast(flip(F.s, F.ss ^ xs), ok);
   } else {
-    double t = F.s / F.c;
-    // relative error of the quotient plus the absolute errors of s and c
-    // magnified by 1/|c|: |dt| <= |t| 2^-52 + (es + |t| ec) / |c|
-    double ic = __builtin_amdgcn_rcp(fabs(F.c));
-    double e = fma(fabs(t), 0x1p-50, (F.es + fabs(t) * F.ec) * ic * 2.0);
+    // t = s / c from the hardware reciprocal and two corrections by exact
+    // residuals (each squares the relative error of the estimate), within
+    // 2^-52 |t|; then the absolute errors of s and c magnified by 1/|c|:
+    // |dt| <= |t| 2^-52 + (es + |t| ec) / |c| (bound with margins)
+    const double ic = __builtin_amdgcn_rcp(F.c);
+    double t = F.s * ic;
+    t = fma(fma(-t, F.c, F.s), ic, t);
+    t = fma(fma(-t, F.c, F.s), ic, t);
+    double e = fma(fabs(t), 0x1p-50, (F.es + fabs(t) * F.ec) * fabs(ic) * 2.0);
     res = round_f32_fast_abs(flip(t, F.ss ^ F.sc ^ xs), e, ok);
   }
   float sp;
