@@ -94,6 +94,17 @@ __device__ __forceinline__ double pow2i(int m) {
 
 __device__ __forceinline__ uint32_t f32_bits(float x) { return __float_as_uint(x); }
 __device__ __forceinline__ float bits_f32(uint32_t b) { return __uint_as_float(b); }
+// a / b from the hardware reciprocal and two corrections by exact residuals,
+// each of which squares the relative error of the estimate: the quotient within
+// 2^-52 |a/b| for b and a/b in the normal range.  Cheaper than the IEEE
+// division sequence where the fast paths' error budgets allow 2^-52.
+__device__ __forceinline__ double div_fast(double a, double b) {
+  const double ib = __builtin_amdgcn_rcp(b);
+  double q = a * ib;
+  q = fma(fma(-q, b, a), ib, q);
+  return fma(fma(-q, b, a), ib, q);
+}
+
 // x quieted (payload and sign kept) when x is a NaN, else v -- an integer
 // select: as a float conditional the compiler branches around the bit operation
 __device__ __forceinline__ float nan_or(float x, float v) {

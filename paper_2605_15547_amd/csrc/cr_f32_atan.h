@@ -41,7 +41,8 @@ __device__ __forceinline__ void atan_ratio_fast(double Y0, double X0, const Atan
   int j = (int)rintf(16.0f * zf);
   j = j > 15 ? 15 : (j < 0 ? 0 : j);
   double c = (double)j * 0.0625;
-  double t = fma(-c, X, Y) / fma(c, Y, X);
+  // the quotient of the rounded num and den within 2^-52 (den >= X > 0)
+  double t = div_fast(fma(-c, X, Y), fma(c, Y, X));
   double t2 = t * t;
   double p = ATAN_P[ATAN_P_DEG];
 #pragma unroll
@@ -52,10 +53,24 @@ __device__ __forceinline__ void atan_ratio_fast(double Y0, double X0, const Atan
   lo = (inv ? T.w : T.y) + (inv ? -at : at);
 }
 
-// Fast-path error: t has relative error <= 3 2^-53 (+ P < 2^-66), so atan t
-// is within 2^-56.7 absolute (|t| <= 1/31); the result is >= |t|/2 for j = 0
-// and >= 0.03 otherwise; with the final addition this is below 4 ulps.  The
-// test uses 16.
+// sqrt(w) for w >= 2^-48 (w = 1 - a^2 for a binary32 a in [0, 1), a multiple
+// of 2^-48): the hardware reciprocal square root refined by Goldschmidt's
+// iteration and two Newton corrections -- the compiler's expansion of sqrt
+// without its rescaling of tiny and special operands, which cannot occur here
+__device__ __forceinline__ double sqrt_unit(double w) {
+  const double y = __builtin_amdgcn_rsq(w);
+  double s = w * y, h = 0.5 * y;
+  const double r = fma(-h, s, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  s = fma(fma(-s, s, w), h, s);
+  return fma(fma(-s, s, w), h, s);
+}
+
+// Fast-path error: t has relative error <= 4 2^-53 (num, den, the quotient;
+// + P < 2^-66), so atan t is within 2^-56 absolute (|t| <= 1/31); the result
+// is >= |t|/2 for j = 0 and >= 0.03 otherwise; with the final addition this is
+// below 5 ulps.  The test uses 16.
 constexpr int ATAN_LOG2E = 4;
 
 // Branch-free: res is always written (meaningful only when true is returned).
@@ -79,7 +94,10 @@ __device__ __forceinline__ float atan_fast(float xf, const AtanTab& tb, bool& ok
     yh = hi + lo;
     if (xf < 0.0f) yh = -yh;
   } else {
-    double s = sqrt(fma(-a, a, 1.0));
+    // |x| = 1 gives w = 0, replaced by 2^-100: asin(+-1) and acos(-1) come out
+    // within 2^-50 of +-pi/2 and pi and round to them (acos(1) and |x| > 1 are
+    // special cases)
+    double s = sqrt_unit(fmax(fma(-a, a, 1.0), 0x1p-100));
     if (KIND == ATANK_ASIN) {
       atan_ratio_fast(a, s, tb, hi, lo);
       yh = hi + lo;

@@ -35,8 +35,8 @@ __device__ __forceinline__ double exp_core_fast(float af, double a, const ExpTab
   (void)af;
 }
 
-// Fast-path error: expm1/exp carry <= 4 ulps; the division and the sums add
-// <= 3; the test uses 32 ulps.
+// Fast-path error: expm1/exp carry <= 4 ulps; the division (div_fast, within
+// 2 ulps) and the sums add <= 4; the test uses 32 ulps.
 constexpr int HYP_LOG2E = 5;
 
 // Branch-free: res is always written (meaningful only when true is returned).
@@ -53,15 +53,15 @@ __device__ __forceinline__ double hyp_value_fast(float xf, const ExpTab& tb) {
   if (KIND == HYPK_SINH) {
     a = fmin(a, 100.0);  // sinh(100) > 2^143 overflows binary32 like sinh(inf)
     double e = exp_core_fast<true>(xf, a, tb);
-    return 0.5 * (e + e / (e + 1.0));
+    return 0.5 * (e + div_fast(e, e + 1.0));
   } else if (KIND == HYPK_COSH) {
     a = fmin(a, 100.0);
     double E = exp_core_fast<false>(xf, a, tb);
-    return 0.5 * (E + 1.0 / E);
+    return 0.5 * (E + div_fast(1.0, E));
   } else {
     a = fmin(a, 20.0);  // tanh(20) = 1 - 2^-57.7 rounds to 1 like tanh(inf)
     double e = exp_core_fast<true>(xf, 2.0 * a, tb);
-    return e / (e + 2.0);
+    return div_fast(e, e + 2.0);
   }
 }
 

@@ -414,10 +414,8 @@ __device__ __forceinline__ float trig_fast(float xf, const TrigTab& tb, bool& ok
     // residuals (each squares the relative error of the estimate), within
     // 2^-52 |t|; then the absolute errors of s and c magnified by 1/|c|:
     // |dt| <= |t| 2^-52 + (es + |t| ec) / |c| (bound with margins)
+    const double t = div_fast(F.s, F.c);
     const double ic = __builtin_amdgcn_rcp(F.c);
-    double t = F.s * ic;
-    t = fma(fma(-t, F.c, F.s), ic, t);
-    t = fma(fma(-t, F.c, F.s), ic, t);
     double e = fma(fabs(t), 0x1p-50, (F.es + fabs(t) * F.ec) * fabs(ic) * 2.0);
     res = round_f32_fast_abs(flip(t, F.ss ^ F.sc ^ xs), e, ok);
   }
