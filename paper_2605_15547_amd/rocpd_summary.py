@@ -1,8 +1,15 @@
 """Summarise rocprofv3 SQLite output (kernel-trace stats, or one PMC counter per
-dispatch) into a short text table.  Usage:
+dispatch) into a short text table, or turn a FETCH_SIZE and a WRITE_SIZE run of
+the same workload into HBM bytes per launch.  Usage:
   python -m paper_2605_15547_amd.rocpd_summary stats   <results.db>
   python -m paper_2605_15547_amd.rocpd_summary counter <results.db>
+  python -m paper_2605_15547_amd.rocpd_summary traffic <fetch.db> <write.db> <copy_bytes>
+         <elems_per_launch> <source_hash>
+traffic calibrates both counters on the largest dispatch of the runtime's
+plain copy kernel (copy_bytes read and written) and prints the text summary,
+then one JSON line (the content of profiles/traffic.json).
 """
+import json
 import re
 import sqlite3
 import sys
@@ -56,7 +63,50 @@ def counter(db):
         print("%-44s %-20s %6d %16.1f" % (k, c, len(v), sum(v) / len(v)))
 
 
+def per_dispatch(db):
+    """{kernel name: [value per dispatch]} of a one-counter run, in KiB"""
+    cols = [r[1] for r in db.execute("pragma table_info(counters_collection)")]
+    agg = defaultdict(list)
+    for r in db.execute("select * from counters_collection"):
+        d = dict(zip(cols, r))
+        agg[d.get("kernel_name", "?")].append(d.get("value"))
+    return agg
+
+
+def traffic(fetch_db, write_db, copy_bytes, elems, source_hash):
+    f, w = per_dispatch(fetch_db), per_dispatch(write_db)
+    copy = [k for k in f if "copyBuffer" in k]
+    if not copy:
+        raise SystemExit("no copy kernel in the fetch run")
+    kib = copy_bytes / 1024.0
+    fscale = kib / max(max(f[k]) for k in copy)
+    wscale = kib / max(max(w[k]) for k in copy if k in w)
+    print("calibration: the largest plain-copy dispatch moves %d bytes each way" % copy_bytes)
+    print("  FETCH_SIZE scale %.3f, WRITE_SIZE scale %.3f" % (fscale, wscale))
+    algo = 8.0 * elems / 1024.0
+    out = {}
+    print("per launch (%d elements, algorithmic 8 B per element = %.0f KiB):" % (elems, algo))
+    for k in sorted(f):
+        m = re.search(r"k_map_f32<(?:\(anonymous namespace\)::)?(\w+(?:<\d+>)?)", k)
+        if not m or m.group(1) not in FUNCS or k not in w:
+            continue
+        fk = sum(f[k]) / len(f[k])
+        wk = sum(w[k]) / len(w[k])
+        tot = fk * fscale + wk * wscale
+        name = FUNCS[m.group(1)]
+        out[name] = int(round(tot * 1024))
+        print("  %-14s %.3f x %.1f + %.3f x %.1f = %.1f KiB (%.4f x algorithmic)"
+              % (name, fscale, fk, wscale, wk, tot, tot / algo))
+    print(json.dumps({"source_hash": source_hash, "elems_per_launch": elems,
+                      "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4),
+                      "hbm_bytes_per_launch": out}))
+
+
 if __name__ == "__main__":
     mode, path = sys.argv[1], sys.argv[2]
-    db = sqlite3.connect(path)
-    stats(db) if mode == "stats" else counter(db)
+    if mode == "traffic":
+        traffic(sqlite3.connect(path), sqlite3.connect(sys.argv[3]), int(sys.argv[4]),
+                int(sys.argv[5]), sys.argv[6])
+    else:
+        db = sqlite3.connect(path)
+        stats(db) if mode == "stats" else counter(db)
