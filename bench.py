@@ -40,6 +40,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK = 256 * 64 * 2.4e9  # lane-instructions/s: one wave64 VALU instruction per CU per cycle
 FAMILY = ["expf", "exp2f", "exp10f", "expm1f", "logf", "log2f", "log10f", "log1pf", "rsqrtf"]
 TRIG = ["sinf", "cosf", "sincosf", "tanf", "asinf", "acosf", "atanf", "sinhf", "coshf", "tanhf"]
 OTHER_LEGS = ("trig", "binary64", "vsulp", "complex", "dft", "batch", "split")
@@ -335,6 +336,19 @@ def measured_traffic(func, n):
     return t["hbm_bytes_per_launch"].get(func)
 
 
+def measured_valu(func, n):
+    """VALU instructions per element of func's kernel from the committed
+    rocprofv3 SQ_INSTS_VALU run, or None when the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "valu.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_source_hash() or t.get("elems_per_launch") != n:
+        return None
+    return t["valu_per_elem"].get(func)
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -524,6 +538,19 @@ def main():
             "frac": round(per[dom]["gb_s"] / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(dom, n),
             "bytes_per_elem": 8, "elems_per_launch": n}
+    # the issue side of the same kernel: VALU instructions per element (from the
+    # committed counter run) x elements per second against the issue rate of
+    # one wave-level VALU instruction per CU per cycle (256 x 64 lanes x 2.4 GHz
+    # = 39.3 T lane-instructions/s, the rate of the 78.6 TFLOP/s binary64 FMA
+    # peak and half the packed binary32 peak of 157.3 TFLOP/s)
+    vpe = measured_valu(dom, n)
+    if vpe is not None:
+        rate = vpe * n / (per[dom]["ms"] * 1e-3)
+        roof["valu"] = {"instr_per_elem": vpe, "achieved_lane_instr_s": round(rate / 1e12, 2),
+                        "peak_lane_instr_s": round(VALU_PEAK / 1e12, 2), "unit": "T/s",
+                        "frac": round(rate / VALU_PEAK, 4)}
+    else:
+        roof["valu"] = None
 
     # the leading outputs of the last timed step, for the check against the
     # oracle results the cpu_baseline leg computes

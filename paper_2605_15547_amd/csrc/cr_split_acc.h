@@ -19,9 +19,10 @@
 //   addition or product contributes below 2^-67 of its larger operand; the
 //   float-float tails stay below 2^-66 of the result).
 //   log1p of |x| < 2^-12 has the one harder pair, x = +-1.5000004 2^-21 at
-//   2^-66.4: there log1p x = x + C with C computed to 2^-46 of itself
-//   (|C| < 2^-12.5 |x|, so below 2^-70 of the result after the exact final
-//   sum) and the bound is TF_EREL_TINY = 2^-68.
+//   2^-66.4: there log1p x = x + C with -x^2/2 exact and the rest of C (below
+//   2^-25.6 |x|) to 2^-46 of itself, the final sum within 2^-71 |x|, so the
+//   result is within about 2^-70.5 of itself and the bound is TF_EREL_TINY =
+//   2^-68.
 // A lane whose bound still straddles a boundary is counted as an escape (the
 // exhaustive scans of all 2^32 inputs find none).
 #pragma once

@@ -5,9 +5,15 @@ the same workload into HBM bytes per launch.  Usage:
   python -m paper_2605_15547_amd.rocpd_summary counter <results.db>
   python -m paper_2605_15547_amd.rocpd_summary traffic <fetch.db> <write.db> <copy_bytes>
          <elems_per_launch> <source_hash>
+  python -m paper_2605_15547_amd.rocpd_summary valu <valu.db> <elems_per_launch> <source_hash>
 traffic calibrates both counters on the largest dispatch of the runtime's
 plain copy kernel (copy_bytes read and written) and prints the text summary,
-then one JSON line (the content of profiles/traffic.json).
+then one JSON line (the content of profiles/traffic.json).  valu reads a run
+with SQ_INSTS_VALU and GRBM_GUI_ACTIVE and prints, per map kernel of
+elems_per_launch elements, VALU instructions per element and the fraction of
+the issue rate used (a CU issues one wave-level VALU instruction per cycle;
+GRBM_GUI_ACTIVE sums the 8 XCDs' busy cycles), then one JSON line (the
+content of profiles/valu.json).
 """
 import json
 import re
@@ -102,9 +108,39 @@ def traffic(fetch_db, write_db, copy_bytes, elems, source_hash):
                       "hbm_bytes_per_launch": out}))
 
 
+def valu(db, elems, source_hash):
+    cols = [r[1] for r in db.execute("pragma table_info(counters_collection)")]
+    per = defaultdict(lambda: defaultdict(list))
+    for r in db.execute("select * from counters_collection"):
+        d = dict(zip(cols, r))
+        per[d.get("kernel_name", "?")][d.get("counter_name")].append(d.get("value"))
+    out = {}
+    print("%-40s %10s %12s" % ("kernel (%d elements per dispatch)" % elems, "VALU/elem",
+                               "issue_util"))
+    for k in sorted(per):
+        m = re.search(r"k_map_f32<(?:\(anonymous namespace\)::)?(\w+(?:<\d+>)?)", k)
+        c = per[k]
+        if not m or m.group(1) not in FUNCS or "SQ_INSTS_VALU" not in c:
+            continue
+        insts = sum(c["SQ_INSTS_VALU"]) / len(c["SQ_INSTS_VALU"])
+        vpe = insts * 64.0 / elems
+        util = None
+        if "GRBM_GUI_ACTIVE" in c:
+            cyc = sum(c["GRBM_GUI_ACTIVE"]) / len(c["GRBM_GUI_ACTIVE"]) / 8.0
+            util = insts / (256.0 * cyc)
+        name = FUNCS[m.group(1)]
+        out[name] = round(vpe, 2)
+        print("%-40s %10.1f %12s" % ("k_map_f32<%s> (%s)" % (m.group(1), name), vpe,
+                                     "-" if util is None else "%.1f%%" % (100 * util)))
+    print(json.dumps({"source_hash": source_hash, "elems_per_launch": elems,
+                      "valu_per_elem": out}))
+
+
 if __name__ == "__main__":
     mode, path = sys.argv[1], sys.argv[2]
-    if mode == "traffic":
+    if mode == "valu":
+        valu(sqlite3.connect(path), int(sys.argv[3]), sys.argv[4])
+    elif mode == "traffic":
         traffic(sqlite3.connect(path), sqlite3.connect(sys.argv[3]), int(sys.argv[4]),
                 int(sys.argv[5]), sys.argv[6])
     else:
