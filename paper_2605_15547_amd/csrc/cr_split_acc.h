@@ -106,7 +106,7 @@ __device__ __forceinline__ tf tfexp_q(tf r) {
   c.lo += TF_SIXTH_M + rb.lo;
   const ff t3 = ff_mul(r3, c);
   const tf s = tf_add_ff(tf_scale(z, 0.5f), t3);
-  return tf_add(r, s);
+  return tf_add_ord(r, s);  // |s| < 2^-10 |r|
 }
 
 template <int K>
@@ -126,7 +126,7 @@ __device__ __noinline__ AccResult sexp_acc(float xf) {
   if (K != EXPK_EM1) {
     // y = T1 T2 (1 + q), in [0.68, 1.42]
     const tf T = tf_mul(tf_tab(TFEXP_T1, dg.i1), tf_tab(TFEXP_T2, dg.i0));
-    const tf y = tf_add(T, tf_mul(T, q));
+    const tf y = tf_add_ord(T, tf_mul(T, q));  // |T q| < 2^-9 |T|
     if (m > -126) {
       res = ldexpf(round32_tf(y, TF_EREL, ok), m);
     } else {  // below 2^-125: integer multiple of 2^-149 (m >= -217)
@@ -172,7 +172,8 @@ __device__ __forceinline__ tf tflog1p_poly(tf t) {
   z2.lo = fmaf(2.0f * z.h, z.m, z2.lo);
   const ff t4 = ff_mul(z2, P4);
   const tf s = tf_add_ff(c3, ff{-t4.hi, -t4.lo});
-  return tf_add(t, tf_add(tf_scale(z, -0.5f), s));
+  // each sum is ordered: |s| < |t| |t^2/2| and |t^2/2| < |t|/2 (|t| < 2^-7.6)
+  return tf_add_ord(t, tf_add_ord(tf_scale(z, -0.5f), s));
 }
 
 template <int K>
@@ -250,8 +251,9 @@ __device__ __noinline__ AccResult slog_acc(float xf) {
       const float k4 = K == LOGK_10 ? TFLOG_LG2_LL : TFLOG_LN2_LL;
       const ff e2 = ff_two_prod(ef, k2);
       const ff e3 = ff_two_prod(ef, k3);
-      const tf E = tf_add(tf_renorm(ef * k1, e2.hi, e2.lo), tf_renorm(e3.hi, e3.lo, ef * k4));
-      L = tf_add(E, Z);
+      const tf E = tf_add_ord(tf_renorm(ef * k1, e2.hi, e2.lo), tf_renorm(e3.hi, e3.lo, ef * k4));
+      // |Z| <= 0.41 < |E| / 1.7 unless e = 0 (then E = 0)
+      L = tf_add_ord(E, Z);
     }
   }
   bool ok;
@@ -324,7 +326,7 @@ __device__ __forceinline__ TfTrig tftrig_core(float xf, const unsigned* w) {
   ff r5 = ff_two_prod(r3.h, zh);
   r5.lo = fmaf(r3.h, z.m, fmaf(r3.m, zh, r5.lo));
   const ff st = ff_mul(r5, s5);
-  const tf sr = tf_add(r, tf_add_ff(tf_neg(r36), st));
+  const tf sr = tf_add_ord(r, tf_add_ff(tf_neg(r36), st));  // |r^3/6 ...| < 2^-8 |r|
   // cos r - 1
   const float c6 = fmaf(fmaf(fmaf(TFTRIG_C12, zh, TFTRIG_C10), zh, TFTRIG_C8), zh, TFTRIG_C6);
   const ff cp = ff_two_prod(zh, c6);
@@ -344,8 +346,11 @@ __device__ __forceinline__ TfTrig tftrig_core(float xf, const unsigned* w) {
   if (quad >= 2) Sv = tf_neg(Sv);
   if (quad == 1 || quad == 2) Cv = tf_neg(Cv);
   // sin x = S + (C sin r + S (cos r - 1)), cos x = C + (C (cos r - 1) - S sin r)
-  o.s = tf_add(Sv, tf_add(tf_mul(Cv, sr), tf_mul(Sv, cm)));
-  o.c = tf_add(Cv, tf_add(tf_mul(Cv, cm), tf_neg(tf_mul(Sv, sr))));
+  // ordered sums: |S (cos r - 1)| <= |C sin r| / 4 and |C (cos r - 1)| <=
+  // |S sin r| / 4 unless the larger term's factor is 0, and the table term
+  // (>= 0.098 unless 0) dominates the rest (<= 0.05)
+  o.s = tf_add_ord(Sv, tf_add_ord(tf_mul(Cv, sr), tf_mul(Sv, cm)));
+  o.c = tf_add_ord(Cv, tf_add_ord(tf_neg(tf_mul(Sv, sr)), tf_mul(Cv, cm)));
   return o;
 }
 
@@ -415,7 +420,8 @@ __device__ __forceinline__ tf tfatan_ratio(tf Y0, tf X0) {
   const ff tail = ff_mul(t5, P);
   const tf at = tf_add(t, tf_add_ff(tf_neg(c3), tail));
   const tf base = tf_tab(inv ? TFATAN_B : TFATAN_A, j);
-  return tf_add(base, inv ? tf_neg(at) : at);
+  // |atan t| <= atan(1/31) <= base/2, or base = 0 (j = 0, not inverted)
+  return tf_add_ord(base, inv ? tf_neg(at) : at);
 }
 
 // sqrt(1 - a^2) as a triple-float, a in [0, 1]: two Newton steps from the
@@ -482,14 +488,14 @@ __device__ __noinline__ AccResult shyp_acc(float xf) {
     const tf D12 = tf_add(tf_add(D1, D2), tf_mul(D1, D2));
     const tf E = tf_add(D12, tf_mul(q, tf_add_f(D12, 1.0f)));
     if (KIND == HYPK_SINH) {  // (E + E/(E + 1))/2
-      v = tf_add(E, tf_div(E, tf_add_f(E, 1.0f)));
+      v = tf_add_ord(E, tf_div(E, tf_add_f(E, 1.0f)));  // 0 <= E/(E + 1) <= E
       sc = -1;
     } else {                  // E/(E + 2)
       v = tf_div(E, tf_add_f(E, 2.0f));
     }
   } else {
     const tf T = tf_mul(tf_tab(TFEXP_T1, dg.i1), tf_tab(TFEXP_T2, dg.i0));
-    const tf Y = tf_add(T, tf_mul(T, q));
+    const tf Y = tf_add_ord(T, tf_mul(T, q));
     // beyond m = 40 the e^-a terms are below 2^-79 of the result: their scale
     // is frozen at m = 40 (tanh then rounds to 1 either way)
     const int mc = m < 40 ? m : 40;
@@ -499,7 +505,7 @@ __device__ __noinline__ AccResult shyp_acc(float xf) {
     } else {                  // 2^(m-1) (y -+ 2^(-2m)/y)
       const float p = pow2f_i(-2 * mc);
       const tf w = tf_scale(tf_div(tf_from(1.0f), Y), p);
-      v = tf_add(Y, KIND == HYPK_SINH ? tf_neg(w) : w);
+      v = tf_add_ord(Y, KIND == HYPK_SINH ? tf_neg(w) : w);  // |w| <= 0.37 Y
       sc = m - 1;
     }
   }

@@ -33,6 +33,18 @@ __device__ __forceinline__ tf tf_renorm(float a, float b, float c) {
   return {v.hi, w.hi, w.lo};
 }
 
+// The same for |b|, |c| below 2^-20 |a| (or a = 0), as in a product whose
+// leading part is a: b + c by TwoSum, a plus that sum's high part by Fast2Sum
+// (exact: a's exponent is not below it), the two low parts by TwoSum.  Exact,
+// and normalised as tf_renorm's result, in three transformations instead of
+// five.
+__device__ __forceinline__ tf tf_renorm_ord(float a, float b, float c) {
+  ff s = ff_two_sum(b, c);
+  ff t = ff_fast_two_sum(a, s.hi);
+  ff u = ff_two_sum(t.lo, s.lo);
+  return {t.hi, u.hi, u.lo};
+}
+
 __device__ __forceinline__ tf tf_from(float a) { return {a, 0.0f, 0.0f}; }
 __device__ __forceinline__ tf tf_from_ff(ff a) { return {a.hi, a.lo, 0.0f}; }
 __device__ __forceinline__ tf tf_neg(tf a) { return {-a.h, -a.m, -a.l}; }
@@ -47,6 +59,17 @@ __device__ __forceinline__ tf tf_add(tf x, tf y) {
   ff t1 = ff_two_sum(s0.lo, s1.hi);
   float t2 = (s1.lo + s2.hi) + (s2.lo + t1.lo);
   return tf_renorm(s0.hi, t1.hi, t2);
+}
+
+// x + y where y cannot cancel x: |y| <= |x|/2, or x = 0 (then the sum is y
+// itself).  The leading parts add by Fast2Sum (x's exponent is not below y's)
+// and the renormalisation needs only the ordered form; one rounding, of the
+// lowest parts, as in tf_add.
+__device__ __forceinline__ tf tf_add_ord(tf x, tf y) {
+  ff s0 = ff_fast_two_sum(x.h, y.h);
+  ff s1 = ff_two_sum(x.m, y.m);
+  ff t1 = ff_two_sum(s0.lo, s1.hi);
+  return tf_renorm_ord(s0.hi, t1.hi, (s1.lo + (x.l + y.l)) + t1.lo);
 }
 
 // x + y for a binary32 y: one rounding, below 2^-71 (|x| + |y|)
@@ -71,14 +94,14 @@ __device__ __forceinline__ tf tf_mul(tf x, tf y) {
   float low = fmaf(x.h, y.l, fmaf(x.m, y.m, x.l * y.h)) + (p01.lo + p10.lo);
   ff m1 = ff_two_sum(p01.hi, p10.hi);
   ff m2 = ff_two_sum(p00.lo, m1.hi);
-  return tf_renorm(p00.hi, m2.hi, (m1.lo + m2.lo) + low);
+  return tf_renorm_ord(p00.hi, m2.hi, (m1.lo + m2.lo) + low);
 }
 
 __device__ __forceinline__ tf tf_mul_f(tf x, float d) {
   ff p0 = ff_two_prod(x.h, d);
   ff p1 = ff_two_prod(x.m, d);
   ff m2 = ff_two_sum(p0.lo, p1.hi);
-  return tf_renorm(p0.hi, m2.hi, fmaf(x.l, d, p1.lo + m2.lo));
+  return tf_renorm_ord(p0.hi, m2.hi, fmaf(x.l, d, p1.lo + m2.lo));
 }
 
 // a / b: three quotient digits from the hardware reciprocal, each followed by
