@@ -33,6 +33,10 @@ for _k in list(FUNCS):
     if _k.startswith("Op") and not _k.endswith("64") and _k[2:3] != "S":
         FUNCS["OpS" + _k[2:]] = FUNCS[_k] + " split"
 FUNCS["SinCosSplit"] = "sincosf split"
+FUNCS["OpLog128"] = "log, 128-entry table"
+# the platform's ~1-ulp functions timed for the paper's ratio (libcr_ulpref.so)
+REF_IDS = {"0": "HIP expf", "4": "HIP logf", "11": "HIP sincosf", "64": "HIP exp", "65": "HIP log",
+           "66": "HIP exp2"}
 
 
 def short(name):
@@ -41,7 +45,8 @@ def short(name):
     m = re.match(r"void (k_\w+)<(\w+(?:<\d+>)?)[ ,>]", name)
     if m:
         op = m.group(2)
-        return "%s<%s> (%s)" % (m.group(1), op, FUNCS.get(op, "?"))
+        what = REF_IDS.get(op, "?") if m.group(1).startswith("k_ref") else FUNCS.get(op, "?")
+        return "%s<%s> (%s)" % (m.group(1), op, what)
     return name.split("(")[0][:60]
 
 
