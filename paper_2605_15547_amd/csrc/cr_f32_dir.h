@@ -119,7 +119,7 @@ __device__ __noinline__ AccResult log_dir(float xf, const LogTab& tb) {
   if (K == LOGK_10) l = dd_mul(l, dd{INV_LN10_HI, INV_LN10_LO});
   dd C = K == LOGK_2 ? dd{1.0, 0.0}
                      : K == LOGK_10 ? dd{LOG10_2_HI, LOG10_2_LO} : dd{LN2_HI, LN2_LO};
-  dd y = dd_add(dd_mul_d(C, (double)S.e2), dd{S.L.x, S.L.y});
+  dd y = dd_add(dd_mul_d(C, (double)S.e2), log_table_dd(S));
   y = dd_add(y, l);
   bool ok;
   float r = round_f32_dd_mode<RM>(y.hi, y.lo, DIR_DREL, ok);

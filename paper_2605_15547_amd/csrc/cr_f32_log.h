@@ -27,12 +27,14 @@ namespace cr {
 
 enum { LOGK_E = 0, LOGK_2 = 1, LOGK_10 = 2, LOGK_1P = 3 };
 
-// One 32-byte row per sub-interval, so that both reads of a lookup share one
-// address (j 32) and differ only in their immediate offsets.
+// One 32-byte row per sub-interval, so that the reads of a lookup share one
+// address (j 32) and differ only in their immediate offsets.  -log_b(c_j) =
+// L.x + L.y + z with L.x a multiple of 2^-44 (2^-45 for log10): e' log_b(2)
+// plus L.x is exact in the fast path; the accurate paths add z back.
 struct LogRow {
-  double2 L;  // -log_b(c_j), double-double
+  double2 L;  // -log_b(c_j): high part, next 53 bits
   double c;   // c_j
-  double pad;
+  double z;   // the rest of -log_b(c_j)
 };
 struct LogTab {
   LogRow row[16];
@@ -43,16 +45,17 @@ __device__ __forceinline__ void log_tab_load(LogTab& t, int tid) {
   if (tid < 16) {
     t.row[tid].L = (K == LOGK_2) ? LOG2_L[tid] : (K == LOGK_10) ? LOG10_L[tid] : LOGE_L[tid];
     t.row[tid].c = LOG_C[tid];
-    t.row[tid].pad = 0.0;
+    t.row[tid].z = (K == LOGK_2) ? LOG2_LZ[tid] : (K == LOGK_10) ? LOG10_LZ[tid] : LOGE_LZ[tid];
   }
 }
 
 // Fast-path error (t and K t are exact: t is a multiple of 2^-33 below 1/16,
 // K has 20 bits).  Q's approximation error (below 2^-57.6) and its Horner
 // evaluation error (below 2^-52 |Q|, |Q| < 0.05) enter through t Q, which is
-// rounded once inside inner (< 2^-53 |t Q|); s = K t + inner is rounded once
-// (half an ulp of s, at most 2^-57) and yh = A.hi + s once more (half an ulp
-// of y).  Summed per interval of the reduction, for e' = 0 (where |y| can be
+// rounded once inside inner = t Q + lo (< 2^-53 |inner|; lo, the low parts of
+// e' log_b(2) and -log_b(c_j), is below 2^-43 and rounded once, the table's
+// third part, below 2^-97, is dropped); s = K t + inner is rounded once (half
+// an ulp of s, at most 2^-57) and yh = Ah + s once more (half an ulp of y).  Summed per interval of the reduction, for e' = 0 (where |y| can be
 // as small as 0.0128 while |s| is not) and e' != 0, over a fine grid of each
 // interval and the three bases, the total stays below 0.82 ulp of y.  A y just
 // above a power of two may give a yh just below it, whose ulp is half as large:
@@ -117,10 +120,18 @@ __device__ __forceinline__ dd log1p_dd_short(dd t) {
 // Shared set-up: u (= x, or 1 + x for log1pf), the decomposition u = 2^e' m
 // with m in [0.75, 1.5), the table entries and the reduced argument t.
 struct LogSetup {
-  double u, m, c, t;
+  double u, m, c, t, z;
   double2 L;
   int e2;
 };
+
+// -log_b(c_j) as a double-double for the accurate paths: hi + lo by Fast2Sum
+// (exact; |lo| < 2^-44 <= |hi| unless both are 0), then the third part
+__device__ __forceinline__ dd log_table_dd(const LogSetup& S) {
+  dd l = fast_two_sum(S.L.x, S.L.y);
+  l.lo += S.z;
+  return l;
+}
 
 template <int K>
 __device__ __forceinline__ LogSetup log_setup(float xf, const LogTab& tb) {
@@ -135,6 +146,7 @@ __device__ __forceinline__ LogSetup log_setup(float xf, const LogTab& tb) {
   S.m = __hiloint2double((hi & 0x000fffff) | ((1023 - fold) << 20), __double2loint(S.u));
   S.c = tb.row[j].c;
   S.L = tb.row[j].L;
+  S.z = tb.row[j].z;
   S.t = fma(S.m, S.c, -1.0);
   return S;
 }
@@ -191,9 +203,13 @@ __device__ __forceinline__ float log_fast(float xf, const LogTab& tb, bool& ok) 
   double t = S.t;
   double Q = log_Q<K>(t);
   double ed = (double)S.e2;
-  dd A = fast_two_sum(ed * log_C_hi<K>(), S.L.x);  // |e' C| >= |L| unless e' = 0
-  double inner = fma(t, Q, A.lo + fma(ed, log_C_lo<K>(), S.L.y));
-  double yh = A.hi + fma(log_K<K>(), t, inner);
+  // e' log_b(2) + (-log_b c_j), high parts: C_hi has 44 bits and e' at most 8,
+  // both terms are multiples of 2^-44 (2^-45 for log10) and their sum is
+  // below 2^8 in magnitude, so the fma is exact
+  const double Ah = fma(ed, log_C_hi<K>(), S.L.x);
+  const double lo = K == LOGK_2 ? S.L.y : fma(ed, log_C_lo<K>(), S.L.y);
+  double inner = fma(t, Q, lo);
+  double yh = Ah + fma(log_K<K>(), t, inner);
   // logf, log2f and log10f round to normal binary32 numbers (or to +0 at 1),
   // log1pf too except for subnormal x, which are left to the accurate path
   float res = round_f32_bits<LOG_TEST_E>(yh, ok);
@@ -225,7 +241,7 @@ __device__ __noinline__ AccResult log_accurate(float xf, const LogTab& tb) {
   if (K == LOGK_10) l = dd_mul(l, dd{INV_LN10_HI, INV_LN10_LO});
   dd C = K == LOGK_2 ? dd{1.0, 0.0}
                      : K == LOGK_10 ? dd{LOG10_2_HI, LOG10_2_LO} : dd{LN2_HI, LN2_LO};
-  dd y = dd_add(dd_mul_d(C, (double)S.e2), dd{S.L.x, S.L.y});
+  dd y = dd_add(dd_mul_d(C, (double)S.e2), log_table_dd(S));
   y = dd_add(y, l);
   // log1p(t) is within 2^-69.9 |t|, and |t| <= 4.9 |y| (|y| >= 0.0128 unless
   // e' = 0 and c_j = 1, where y is log1p(t) / ln b): y is within 2^-67.5 of

@@ -250,9 +250,27 @@ def gen_log():
     bases = [("E", mp.mpf(1), mp.mpf(1)),
              ("2", 1 / mp.log(2), mp.mpf(split_bits(1 / mp.log(2), 20))),
              ("10", 1 / mp.log(10), mp.mpf(split_bits(1 / mp.log(10), 20)))]
+    # -log_b(c_j) in three parts: hi a multiple of 2^-44 (2^-45 for b = 10), so
+    # that e' C_hi + hi is exact (both multiples of that quantum, the sum below
+    # 2^8), then lo = RN(rest) and z = RN(rest - lo) (for the accurate paths)
     for name, inv_ln, K in bases:
-        emit_dd_table("LOG%s_L" % name, [-mp.log(c) * inv_ln for _, _, c in iv],
-                      "-log_b(c_j), b = %s, double-double" % ("e" if name == "E" else name))
+        q = mp.mpf(2) ** (-45 if name == "10" else -44)
+        his, los, zs = [], [], []
+        for _, _, c in iv:
+            v = -mp.log(c) * inv_ln
+            hi = float(mp.nint(v / q) * q)
+            r = v - mp.mpf(hi)
+            lo = float(r)
+            his.append(hi)
+            los.append(lo)
+            zs.append(float(r - mp.mpf(lo)))
+        b = "e" if name == "E" else name
+        emit("// -log_b(c_j), b = %s: {hi (a multiple of 2^%d), lo}" % (b, -45 if name == "10" else -44))
+        emit("__device__ __constant__ const double2 LOG%s_L[16] = {" % name)
+        for hi, lo in zip(his, los):
+            emit("  {%s, %s}," % (hexd(hi), hexd(lo)))
+        emit("};")
+        emit_arr("LOG%s_LZ" % name, zs, "-log_b(c_j) - hi - lo, b = %s" % b)
     # e' * C with C_hi on 44 bits so that e' C_hi is exact for |e'| < 2^9
     for name, v in (("E", mp.log(2)), ("10", mp.log10(2))):
         hi = split_bits(v, 44)
