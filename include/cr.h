@@ -263,7 +263,12 @@ int cr_stats_read(void *stream, cr_stats *out);
  * LDS per workgroup, or read from one device-global copy through the vector
  * caches) -- and the persistent grid size in workgroups per compute unit.
  * Results never depend on the configuration, only speed does.  sincosf and
- * the binary64 functions have variant 0 only (their grid is tunable).
+ * the complex functions have variant 0 only (their grid is tunable).  The
+ * binary64 functions have variants 0..3 of their own kernel: 0 = 8 doubles
+ * per thread (4 double2 loads per tile), each element evaluated and queued
+ * before the next; 1, 2, 3 = 2, 4, 8 doubles per thread, all elements of the
+ * tile evaluated in straight-line code before the failing ones are queued.
+ * cr_tune_variant_info describes the binary32 variants.
  * Configurations are process-wide host state shared by all devices. */
 typedef struct {
   int32_t variant;       /* 0 .. cr_tune_num_variants()-1; 0 is the default */

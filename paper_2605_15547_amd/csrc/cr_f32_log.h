@@ -191,8 +191,10 @@ __device__ __forceinline__ bool log_special_fast(float xf, float& res) {
 // the way 1 + x is exact in binary64 for every remaining x below 2^29, and the
 // result is a normal binary32 number, as the bit test requires.
 __device__ __forceinline__ bool log1p_special_fast(float xf, float& res) {
-  const float q = __builtin_canonicalizef(xf);
-  res = xf <= -1.0f ? (xf == -1.0f ? -INFINITY : bits_f32(0x7fc00000u)) : q;
+  const uint32_t q = f32_bits(__builtin_canonicalizef(xf));
+  // integer selects: as float conditionals the compiler branches around them
+  const uint32_t v = f32_bits(xf) == 0xbf800000u ? 0xff800000u : 0x7fc00000u;
+  res = bits_f32(xf <= -1.0f ? v : q);
   // NaN and infinities (class mask), tiny arguments, everything at or below -1
   return __builtin_amdgcn_class(xf, 0x207) | (fabsf(xf) < 0x1p-25f) | (xf <= -1.0f);
 }

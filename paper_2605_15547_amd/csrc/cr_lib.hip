@@ -728,11 +728,14 @@ __device__ __forceinline__ void flush_queue64(Deferred64& q, const typename Op::
   });
 }
 
-// The binary64 form of k_map_f32: tiles of 2048 doubles, four 128-bit
-// double2 vectors per thread.
-constexpr int TILE64_U = 4;
-
-template <class Op>
+// The binary64 form of k_map_f32: tiles of BLOCK U double2 vectors (U per
+// thread).  Launch-shape variants (chosen per function by the autotuner):
+//   SL 0: each element is evaluated and, if its test fails, queued before the
+//         next one (a branch between elements),
+//   SL 1: as in k_map_f32, every element of the tile is evaluated in
+//         straight-line code first (the scheduler interleaves their
+//         dependency chains) and the failing ones are queued afterwards.
+template <class Op, int U, int SL>
 __global__ void __launch_bounds__(BLOCK)
     k_map_f64(const double2* in, double2* out, long long n2, DevStats* st, unsigned flags,
               long long elem_base) {
@@ -746,43 +749,74 @@ __global__ void __launch_bounds__(BLOCK)
   __syncthreads();
   const bool force = flags & CR_FLAG_FORCE_FALLBACK;
   double* outd = reinterpret_cast<double*>(out);
-  const long long ntiles = (n2 + BLOCK * TILE64_U - 1) / (BLOCK * TILE64_U);
+  const long long ntiles = (n2 + BLOCK * U - 1) / (BLOCK * U);
+  // queue element j (index 2 i + c of this launch) with input x, or run its
+  // accurate path in place when the queue is full
+  auto enqueue = [&](long long j, double x, double& res) {
+    unsigned pos = atomicAdd(&q.n, 1u);
+    if (pos < QCAP) {
+      q.idx[pos] = (unsigned)j;
+      q.x[pos] = x;
+    } else {
+      AccResultD a = Op::accurate(x, tab);
+      res = a.r;
+      atomicAdd(&q.lanes, 1u);
+      if (!a.ok) note_escape(st, elem_base + j);
+    }
+  };
   int iter = 0;
   for (long long t = blockIdx.x; t < ntiles; t += gridDim.x, iter++) {
-    long long base = t * (BLOCK * TILE64_U) + threadIdx.x;
-    double2 v[TILE64_U];
+    long long base = t * (BLOCK * U) + threadIdx.x;
+    double2 v[U];
 #pragma unroll
-    for (int u = 0; u < TILE64_U; u++) {
+    for (int u = 0; u < U; u++) {
       long long i = base + (long long)u * BLOCK;
-      if (i < n2) v[u] = ld_stream(in + i);
+      v[u] = i < n2 ? ld_stream(in + i) : make_double2(1.0, 1.0);
     }
+    if (SL) {
+      // slots past the end hold 1.0: evaluated, never stored or queued
+      double xin[2 * U];
+      unsigned fail = 0;
 #pragma unroll
-    for (int u = 0; u < TILE64_U; u++) {
-      long long i = base + (long long)u * BLOCK;
-      if (i < n2) {
+      for (int u = 0; u < U; u++) {
+        const bool live = base + (long long)u * BLOCK < n2;
         double* e = reinterpret_cast<double*>(&v[u]);
 #pragma unroll
         for (int c = 0; c < 2; c++) {
           bool ok;
-          double x = e[c];
-          e[c] = Op::fast(x, tab, ok);
-          if (!ok || force) {
-            unsigned pos = atomicAdd(&q.n, 1u);
-            if (pos < QCAP) {
-              q.idx[pos] = (unsigned)(2 * i + c);
-              q.x[pos] = x;
-            } else {
-              AccResultD a = Op::accurate(x, tab);
-              e[c] = a.r;
-              atomicAdd(&q.lanes, 1u);
-              if (!a.ok) note_escape(st, elem_base + 2 * i + c);
-            }
+          xin[2 * u + c] = e[c];
+          e[c] = Op::fast(e[c], tab, ok);
+          fail |= (unsigned)(live && (!ok || force)) << (2 * u + c);
+        }
+      }
+      if (fail) {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          double* e = reinterpret_cast<double*>(&v[u]);
+          const long long i = base + (long long)u * BLOCK;
+#pragma unroll
+          for (int c = 0; c < 2; c++)
+            if ((fail >> (2 * u + c)) & 1u) enqueue(2 * i + c, xin[2 * u + c], e[c]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; u++) {
+        long long i = base + (long long)u * BLOCK;
+        if (i < n2) {
+          double* e = reinterpret_cast<double*>(&v[u]);
+#pragma unroll
+          for (int c = 0; c < 2; c++) {
+            bool ok;
+            double x = e[c];
+            e[c] = Op::fast(x, tab, ok);
+            if (!ok || force) enqueue(2 * i + c, x, e[c]);
           }
         }
       }
     }
 #pragma unroll
-    for (int u = 0; u < TILE64_U; u++) {
+    for (int u = 0; u < U; u++) {
       long long i = base + (long long)u * BLOCK;
       if (i < n2) st_stream(out + i, v[u]);
     }
@@ -1607,7 +1641,7 @@ int launch_sincos(const float* in, float* out, size_t n, hipStream_t s, unsigned
   return CR_OK;
 }
 
-template <class Op>
+template <class Op, int U, int SL>
 int launch_map_f64(const double* in, double* out, size_t n, hipStream_t s, unsigned flags,
                    DevStats* st, int grid) {
   uintptr_t ai = (uintptr_t)in, ao = (uintptr_t)out;
@@ -1629,10 +1663,10 @@ int launch_map_f64(const double* in, double* out, size_t n, hipStream_t s, unsig
   for (size_t done = 0; done < body2;) {
     size_t chunk2 = body2 - done;
     if (chunk2 > ((size_t)1 << 30)) chunk2 = (size_t)1 << 30;
-    size_t tiles = (chunk2 + BLOCK * TILE64_U - 1) / (BLOCK * TILE64_U);
+    size_t tiles = (chunk2 + BLOCK * U - 1) / (BLOCK * U);
     size_t g = tiles < (size_t)grid ? tiles : (size_t)grid;
     size_t off = head + 2 * done;
-    hipLaunchKernelGGL(k_map_f64<Op>, dim3((unsigned)g), dim3(BLOCK), 0, s,
+    hipLaunchKernelGGL((k_map_f64<Op, U, SL>), dim3((unsigned)g), dim3(BLOCK), 0, s,
                        reinterpret_cast<const double2*>(in + off),
                        reinterpret_cast<double2*>(out + off), (long long)chunk2, st, flags,
                        (long long)off);
@@ -1646,6 +1680,21 @@ int launch_map_f64(const double* in, double* out, size_t n, hipStream_t s, unsig
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e);
   return CR_OK;
+}
+
+// The binary64 launch variants: {U, SL} of k_map_f64 (variant 0: four vectors
+// per thread, an element at a time).
+constexpr int NVARIANT64 = 4;
+template <class Op>
+int launch_variant64(const double* in, double* out, size_t n, hipStream_t s, unsigned flags,
+                     DevStats* st, int variant, int grid) {
+  switch (variant) {
+    case 0: return launch_map_f64<Op, 4, 0>(in, out, n, s, flags, st, grid);
+    case 1: return launch_map_f64<Op, 1, 1>(in, out, n, s, flags, st, grid);
+    case 2: return launch_map_f64<Op, 2, 1>(in, out, n, s, flags, st, grid);
+    case 3: return launch_map_f64<Op, 4, 1>(in, out, n, s, flags, st, grid);
+  }
+  return CR_E_TUNE;
 }
 
 // Complex binary32 map (n complex numbers, interleaved): 16-byte aligned
@@ -1828,8 +1877,11 @@ int fidx(int f) {
   return 0;  // not reached: callers validate f first
 }
 int iidx(int impl) { return impl == CR_IMPL_SPLIT_F32 ? 1 : 0; }
-// sincos and the binary64 functions have one kernel shape (variant 0 only)
-int num_variants_of(int f) { return (f == CR_SINCOSF || f >= 64) ? 1 : NVARIANT; }
+// sincos and the complex functions have one kernel shape (variant 0 only),
+// the binary64 functions NVARIANT64
+int num_variants_of(int f) {
+  return (f == CR_SINCOSF || func_complex(f)) ? 1 : f >= 64 ? NVARIANT64 : NVARIANT;
+}
 
 int eval_cfg(int func_id, int impl, unsigned flags, const void* in, void* out, size_t n,
              hipStream_t s, int variant, int bpc) {
@@ -1845,11 +1897,11 @@ int eval_cfg(int func_id, int impl, unsigned flags, const void* in, void* out, s
   else if (func_id < CR_NUM_F32)
     rc = dispatch_f32(func_id, (const float*)in, (float*)out, n, s, flags, st, variant, g);
   else if (func_id == CR_EXP)
-    rc = launch_map_f64<OpExp64>((const double*)in, (double*)out, n, s, flags, st, g);
+    rc = launch_variant64<OpExp64>((const double*)in, (double*)out, n, s, flags, st, variant, g);
   else if (func_id == CR_EXP2)
-    rc = launch_map_f64<OpExp2_64>((const double*)in, (double*)out, n, s, flags, st, g);
+    rc = launch_variant64<OpExp2_64>((const double*)in, (double*)out, n, s, flags, st, variant, g);
   else if (func_id == CR_LOG && impl == CR_IMPL_LOG128)
-    rc = launch_map_f64<OpLog128>((const double*)in, (double*)out, n, s, flags, st, g);
+    rc = launch_variant64<OpLog128>((const double*)in, (double*)out, n, s, flags, st, variant, g);
   else if (func_id == CR_CEXPF)
     rc = launch_complex<CExpF>((const float*)in, (float*)out, n, s, flags, st, g);
   else if (func_id == CR_CLOGF)
@@ -1857,7 +1909,7 @@ int eval_cfg(int func_id, int impl, unsigned flags, const void* in, void* out, s
   else if (func_id == CR_CSINF)
     rc = launch_complex<CSinF>((const float*)in, (float*)out, n, s, flags, st, g);
   else
-    rc = launch_map_f64<OpLog64>((const double*)in, (double*)out, n, s, flags, st, g);
+    rc = launch_variant64<OpLog64>((const double*)in, (double*)out, n, s, flags, st, variant, g);
   if (rc == CR_OK) {
     int dev = 0;
     (void)hipGetDevice(&dev);

@@ -145,7 +145,7 @@ def test_tuning_table(L, tmp_path):
     assert C.tune_get("logf", C.IMPL_AUTO) == (2, 8)  # AUTO is the binary64-internal table
     assert C.tune_get("logf", C.IMPL_SPLIT_F32) == (0, 16)
     for func, impl, v, b in (("expf", 1, len(vs), 16), ("expf", 1, -1, 16), ("expf", 1, 0, 65),
-                             ("sincosf", 1, 1, 16), ("exp", 1, 2, 16)):
+                             ("sincosf", 1, 1, 16), ("exp", 1, 4, 16), ("cexpf", 1, 1, 16)):
         with pytest.raises(C.CrError) as e:
             C.tune_set(func, impl, v, b)
         assert e.value.status == -10
@@ -169,9 +169,10 @@ def test_tuning_table(L, tmp_path):
     with pytest.raises(C.CrError):
         C.tune_load(str(tmp_path / "missing.txt"))
     ok = tmp_path / "ok.txt"
-    ok.write_text("  # comment\n\nexpf split 6 4\nexp f64 0 2\n")
+    ok.write_text("  # comment\n\nexpf split 6 4\nexp f64 3 2\n")
     C.tune_load(str(ok))
-    assert C.tune_get("expf", C.IMPL_SPLIT_F32) == (6, 4) and C.tune_get("exp") == (0, 2)
+    # the binary64 functions have variants 0..3 of their own kernel
+    assert C.tune_get("expf", C.IMPL_SPLIT_F32) == (6, 4) and C.tune_get("exp") == (3, 2)
     C.tune_reset()
     # the autotuner validates its arguments before touching the GPU
     vp = ctypes.c_void_p

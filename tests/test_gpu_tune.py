@@ -50,6 +50,30 @@ def test_every_variant_is_bit_exact(oracle, func, impl):
     assert_same(func, x, gpu_eval(func, x, impl=impl, flags=crmath.FLAG_FORCE_FALLBACK), ref)
 
 
+# the binary64 kernel's own variants (cr.h: 0..3)
+N64_VARIANTS = 4
+
+
+@pytest.mark.parametrize("func,impl", [("exp", crmath.IMPL_F64_INTERNAL),
+                                       ("log", crmath.IMPL_F64_INTERNAL),
+                                       ("exp2", crmath.IMPL_F64_INTERNAL),
+                                       ("log", crmath.IMPL_LOG128)])
+def test_every_binary64_variant_is_bit_exact(oracle, func, impl):
+    _need_gpu()
+    # several tiles per workgroup at the smallest grid, a ragged tail (odd n),
+    # an unaligned head, and the forced accurate path on every variant
+    x = inputs.workload_f64(func, 200_003, seed=31_500)
+    ref = oracle.evaluate(func, x)
+    for v in range(N64_VARIANTS):
+        for bpc in (1, 16):
+            crmath.tune_set(func, impl, v, bpc)
+            assert_same(func, x, gpu_eval(func, x, impl=impl), ref)
+        assert_same(func, x, gpu_eval(func, x, impl=impl, offset_in=1, offset_out=1), ref)
+        assert_same(func, x, gpu_eval(func, x, impl=impl, flags=crmath.FLAG_FORCE_FALLBACK), ref)
+    with pytest.raises(Exception):
+        crmath.tune_set(func, impl, N64_VARIANTS, 16)
+
+
 @pytest.mark.parametrize("func,impl", [("expf", 1), ("sincosf", 1), ("exp", 1), ("logf", 2)])
 def test_autotune_installs_a_correct_configuration(oracle, func, impl):
     _need_gpu()
@@ -66,7 +90,7 @@ def test_autotune_installs_a_correct_configuration(oracle, func, impl):
                            stream_ptr=crmath._stream_ptr(None))
     assert rate > 0
     v, b = crmath.tune_get(func, impl)
-    nv = 1 if func in ("sincosf", "exp", "log") else len(crmath.tune_variants())
+    nv = 1 if func == "sincosf" else N64_VARIANTS if func in F64 else len(crmath.tune_variants())
     assert 0 <= v < nv and b in (2, 4, 8, 16, 32)
     idx = inputs.Stream(5).below(4096, n)
     got = gpu_eval(func, x, impl=impl)
