@@ -301,7 +301,8 @@ def bench_batch(torch, crmath, inputs, steps, warmup, stream, impl=1):
     r = {"impl": "split_f32" if impl == 2 else "f64_internal",
          "requests": len(reqs), "elements": total, "ms": round(ms, 3),
          "gelem_s": round(total / (ms * 1e-3) / 1e9, 2), "gb_s": round(gbs, 1),
-         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "plan_create_s": round(create_s, 3)}
+         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "plan_create_s": round(create_s, 3),
+         "blocks_per_cu": crmath.tune_batch_get(impl)}
     log("bench: batch", r)
     del bufs
     torch.cuda.empty_cache()

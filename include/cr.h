@@ -284,9 +284,18 @@ int cr_tune_get(int func_id, int impl, cr_tune_cfg *cfg);
 int cr_tune_set(int func_id, int impl, const cr_tune_cfg *cfg);
 /* All configurations back to the defaults. */
 int cr_tune_reset(void);
-/* Text file, one line per entry: "<function> <f64|split> <variant> <blocks_per_cu>";
- * '#' starts a comment line.  Load applies nothing unless the whole file is
- * valid (CR_E_TUNE otherwise); save writes every entry. */
+/* Grid of the batch kernels (cr_batch_plan_create, cr_eval_batch,
+ * cr_eval_batch_noalloc): workgroups per compute unit of each per-function
+ * kernel of a batch, one setting per implementation (CR_IMPL_AUTO means
+ * F64_INTERNAL), 1..64, default 4.  A plan keeps the value in force when it is
+ * created.  Results never depend on it.  CR_E_IMPL / CR_E_NULL / CR_E_TUNE on
+ * bad input. */
+int cr_tune_batch_get(int impl, int32_t *blocks_per_cu);
+int cr_tune_batch_set(int impl, int32_t blocks_per_cu);
+/* Text file, one line per entry: "<function> <f64|split> <variant> <blocks_per_cu>",
+ * and "batch <f64|split> 0 <blocks_per_cu>" for the batch grid; '#' starts a
+ * comment line.  Load applies nothing unless the whole file is valid
+ * (CR_E_TUNE otherwise); save writes every entry. */
 int cr_tune_load(const char *path);
 int cr_tune_save(const char *path);
 /* Time every variant x grid size {2, 4, 8, 16, 32 workgroups per CU} of

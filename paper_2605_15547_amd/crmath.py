@@ -44,7 +44,7 @@ EXPORTED = ["cr_eval", "cr_eval_ex", "cr_available", "cr_batch_plan_create",
             "cr_stats_reset",
             "cr_stats_read", "cr_status_str", "cr_last_hip_error", "cr_tune_num_variants",
             "cr_tune_variant_info", "cr_tune_get", "cr_tune_set", "cr_tune_reset", "cr_tune_load",
-            "cr_tune_save", "cr_autotune"]
+            "cr_tune_save", "cr_autotune", "cr_tune_batch_get", "cr_tune_batch_set"]
 
 
 class CrError(RuntimeError):
@@ -106,6 +106,8 @@ def lib():
         L.cr_tune_variant_info.argtypes = [ctypes.c_int, ip, ip, ip]
         L.cr_tune_get.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(TuneCfg)]
         L.cr_tune_set.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(TuneCfg)]
+        L.cr_tune_batch_get.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int32)]
+        L.cr_tune_batch_set.argtypes = [ctypes.c_int, ctypes.c_int32]
         L.cr_tune_load.argtypes = [ctypes.c_char_p]
         L.cr_tune_save.argtypes = [ctypes.c_char_p]
         L.cr_autotune.argtypes = [ctypes.c_int, ctypes.c_int, vp, vp, sz, ctypes.c_int, vp,
@@ -274,6 +276,21 @@ def tune_set(func, impl, variant, blocks_per_cu):
 
 def tune_reset():
     lib().cr_tune_reset()
+
+
+def tune_batch_get(impl=IMPL_AUTO):
+    """Workgroups per CU of the batch kernels of one implementation."""
+    b = ctypes.c_int32()
+    rc = lib().cr_tune_batch_get(impl, ctypes.byref(b))
+    if rc != CR_OK:
+        raise CrError(rc, "cr_tune_batch_get")
+    return b.value
+
+
+def tune_batch_set(impl, blocks_per_cu):
+    rc = lib().cr_tune_batch_set(impl, blocks_per_cu)
+    if rc != CR_OK:
+        raise CrError(rc, "cr_tune_batch_set")
 
 
 def tune_load(path):

@@ -2024,16 +2024,20 @@ void launch_tiles_op(const BReq* r, const BTile* t, const BRange& g, int grid, D
   hipLaunchKernelGGL(k_tiles<Op>, dim3(grid), dim3(BLOCK), 0, s, r, t, g.t0, g.t1, st, flags);
 }
 
-// Workgroups per compute unit of each batch kernel.  The plan's graph runs up
-// to four of them at a time (parallel branches), so together they hold about
-// 16 workgroups per CU; measured on the 4096-request workload: 1 -> 361,
-// 2 -> 413, 4 -> 428, 8 -> 422, 16 -> 411, 32 -> 385 Gelem/s.
-constexpr int BATCH_BPC = 4;
+// Workgroups per compute unit of each batch kernel, per implementation
+// (binary64-internal, binary32-only): a tuned setting (cr_tune_batch_set, the
+// "batch" lines of the tuning file).  The plan's graph runs up to four kernels
+// at a time (parallel branches), so together they hold about four times as
+// many workgroups per CU; the default, 4, was the best of {1, 2, 4, 8, 16, 32}
+// on the 4096-request workload when it was chosen (1 -> 361, 2 -> 413,
+// 4 -> 428, 8 -> 422, 16 -> 411, 32 -> 385 Gelem/s).
+constexpr int BATCH_BPC_DEFAULT = 4;
+std::atomic<int> g_batch_bpc[2] = {BATCH_BPC_DEFAULT, BATCH_BPC_DEFAULT};
 
 // Launch the kernel of one key range (at most one workgroup per tile).
 int launch_tiles(const BReq* r, const BTile* t, const BRange& g, DevStats* st, unsigned flags,
                  hipStream_t s) {
-  long long grid = (long long)num_cus() * BATCH_BPC;
+  long long grid = (long long)num_cus() * g_batch_bpc[g.key >= BSPLIT ? 1 : 0].load();
   if (grid > g.t1 - g.t0) grid = g.t1 - g.t0;
   const int G = (int)grid;
   switch (g.key) {
@@ -2160,11 +2164,27 @@ int cr_tune_set(int func_id, int impl, const cr_tune_cfg* cfg) {
 }
 
 int cr_tune_reset(void) {
-  for (int i = 0; i < 2; i++)
+  for (int i = 0; i < 2; i++) {
     for (int f = 0; f < NFUNC_IDX; f++) {
       g_cfg_variant[i][f] = 0;
       g_cfg_bpc[i][f] = 0;
     }
+    g_batch_bpc[i] = BATCH_BPC_DEFAULT;
+  }
+  return CR_OK;
+}
+
+int cr_tune_batch_get(int impl, int32_t* blocks_per_cu) {
+  if (!impl_valid(impl) || impl == CR_IMPL_LOG128) return CR_E_IMPL;
+  if (!blocks_per_cu) return CR_E_NULL;
+  *blocks_per_cu = g_batch_bpc[iidx(impl)].load();
+  return CR_OK;
+}
+
+int cr_tune_batch_set(int impl, int32_t blocks_per_cu) {
+  if (!impl_valid(impl) || impl == CR_IMPL_LOG128) return CR_E_IMPL;
+  if (blocks_per_cu < 1 || blocks_per_cu > 64) return CR_E_TUNE;
+  g_batch_bpc[iidx(impl)] = blocks_per_cu;
   return CR_OK;
 }
 
@@ -2179,6 +2199,8 @@ int cr_tune_save(const char* path) {
       fprintf(fp, "%s %s %d %d\n", FUNC_NAMES[f], i ? "split" : "f64", g_cfg_variant[i][f].load(),
               b > 0 ? b : default_bpc());
     }
+  for (int i = 0; i < 2; i++)
+    fprintf(fp, "batch %s 0 %d\n", i ? "split" : "f64", g_batch_bpc[i].load());
   int bad = ferror(fp);
   if (fclose(fp) != 0 || bad) return CR_E_TUNE;
   return CR_OK;
@@ -2207,6 +2229,14 @@ int cr_tune_load(const char* path) {
       if (!strcmp(fname, FUNC_NAMES[k])) f = func_of_idx(k);
     int impl = !strcmp(iname, "f64") ? CR_IMPL_F64_INTERNAL
                : !strcmp(iname, "split") ? CR_IMPL_SPLIT_F32 : -1;
+    if (!strcmp(fname, "batch")) {  // the batch kernels' grid: variant 0 only
+      if (impl < 0 || v != 0 || b < 1 || b > 64) {
+        rc = CR_E_TUNE;
+        break;
+      }
+      es.push_back({impl, -1, v, b});
+      continue;
+    }
     cr_tune_cfg c = {v, b};
     if (f < 0 || impl < 0 || tune_check(f, impl, &c) != CR_OK) {
       rc = CR_E_TUNE;
@@ -2217,6 +2247,10 @@ int cr_tune_load(const char* path) {
   fclose(fp);
   if (rc) return rc;  // nothing applied from a malformed file
   for (const Entry& e : es) {
+    if (e.func < 0) {
+      g_batch_bpc[iidx(e.impl)] = e.bpc;
+      continue;
+    }
     g_cfg_variant[iidx(e.impl)][fidx(e.func)] = e.variant;
     g_cfg_bpc[iidx(e.impl)][fidx(e.func)] = e.bpc;
   }

@@ -169,10 +169,31 @@ def test_tuning_table(L, tmp_path):
     with pytest.raises(C.CrError):
         C.tune_load(str(tmp_path / "missing.txt"))
     ok = tmp_path / "ok.txt"
-    ok.write_text("  # comment\n\nexpf split 6 4\nexp f64 3 2\n")
+    # the batch grid: one setting per implementation, in the same file
+    assert C.tune_batch_get() == 4 and C.tune_batch_get(C.IMPL_SPLIT_F32) == 4
+    C.tune_batch_set(C.IMPL_SPLIT_F32, 9)
+    assert C.tune_batch_get(C.IMPL_SPLIT_F32) == 9 and C.tune_batch_get(C.IMPL_F64_INTERNAL) == 4
+    for impl, b in ((C.IMPL_F64_INTERNAL, 0), (C.IMPL_F64_INTERNAL, 65), (C.IMPL_LOG128, 4),
+                    (7, 4)):
+        with pytest.raises(C.CrError):
+            C.tune_batch_set(impl, b)
+    C.tune_save(p)
+    assert "batch split 0 9" in open(p).read().splitlines()
+    C.tune_reset()
+    assert C.tune_batch_get(C.IMPL_SPLIT_F32) == 4
+    C.tune_load(p)
+    assert C.tune_batch_get(C.IMPL_SPLIT_F32) == 9
+    for text in ("batch f64 1 4\n", "batch f64 0 0\n", "batch f32 0 4\n", "batch f64 0\n"):
+        bad.write_text(text)
+        with pytest.raises(C.CrError):
+            C.tune_load(str(bad))
+    assert C.tune_batch_get(C.IMPL_SPLIT_F32) == 9  # nothing applied
+    C.tune_reset()
+    ok.write_text("  # comment\n\nexpf split 6 4\nexp f64 3 2\nbatch f64 0 2\n")
     C.tune_load(str(ok))
     # the binary64 functions have variants 0..3 of their own kernel
     assert C.tune_get("expf", C.IMPL_SPLIT_F32) == (6, 4) and C.tune_get("exp") == (3, 2)
+    assert C.tune_batch_get() == 2
     C.tune_reset()
     # the autotuner validates its arguments before touching the GPU
     vp = ctypes.c_void_p

@@ -91,6 +91,29 @@ def test_batch_unaligned_and_forced(oracle):
     plan.destroy()
 
 
+@pytest.mark.parametrize("bpc", [1, 16])
+def test_batch_grid_sizes(oracle, bpc):
+    """The batch grid (cr_tune_batch_set) changes only the speed: plans made
+    at 1 and 16 workgroups per CU, and cr_eval_batch, give the oracle's bits."""
+    _need_gpu()
+    items = make_requests(200, 5150 + bpc, 14, extra=[("sincosf", 2051), ("atanf", 4099)])
+    try:
+        for impl in (crmath.IMPL_F64_INTERNAL, crmath.IMPL_SPLIT_F32):
+            crmath.tune_batch_set(impl, bpc)
+        plan = crmath.BatchPlan(req_list(items, lambda k: 1 + k % 2))
+        plan.launch()
+        torch.cuda.synchronize()
+        check(items, oracle, "plan at %d WG/CU" % bpc)
+        plan.destroy()
+        for it in items:
+            it["out"].fill_(-3.0)
+        crmath.eval_batch(req_list(items))
+        torch.cuda.synchronize()
+        check(items, oracle, "eval_batch at %d WG/CU" % bpc)
+    finally:
+        crmath.tune_reset()
+
+
 def test_eval_batch(oracle):
     _need_gpu()
     items = make_requests(150, 5300, 13)
