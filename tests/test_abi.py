@@ -220,9 +220,13 @@ def test_committed_tuning_file_is_valid(L):
                 f, impl, v, b = line.split()
                 seen.add((f, impl))
                 im = C.IMPL_SPLIT_F32 if impl == "split" else C.IMPL_F64_INTERNAL
-                assert C.tune_get(f, im) == (int(v), int(b))
+                if f == "batch":
+                    assert C.tune_batch_get(im) == int(b) and int(v) == 0
+                else:
+                    assert C.tune_get(f, im) == (int(v), int(b))
         for f in C.FUNCS32:
             assert (f, "f64") in seen and (f, "split") in seen, f
         assert ("exp", "f64") in seen and ("log", "f64") in seen
+        assert ("batch", "f64") in seen and ("batch", "split") in seen
     finally:
         C.tune_reset()
