@@ -70,8 +70,12 @@ __device__ __forceinline__ double sqrt_unit(double w) {
 // Fast-path error: t has relative error <= 4 2^-53 (num, den, the quotient;
 // + P < 2^-66), so atan t is within 2^-56 absolute (|t| <= 1/31); the result
 // is >= |t|/2 for j = 0 and >= 0.03 otherwise; with the final addition this is
-// below 5 ulps.  The test uses 16.
-constexpr int ATAN_LOG2E = 4;
+// below 5 ulps, 10 ulps of yh when yh falls just below a power of two.  The
+// bit test of cr_round.h rejects yh within 16 ulps of the midpoint pattern
+// (sound below 17 ulps).  It needs results that round to normal binary32
+// numbers: the tiny arguments whose results could be subnormal are special
+// cases of the fast path (atan_special_fast), and acos is at least 2^-11.5.
+constexpr unsigned ATAN_TEST_E = 16;
 
 // Branch-free: res is always written (meaningful only when true is returned).
 __device__ __forceinline__ bool atan_special(float xf, int kind, float& res) {
@@ -82,6 +86,23 @@ __device__ __forceinline__ bool atan_special(float xf, int kind, float& res) {
   float v = zero ? xf : (one ? 0.0f : bits_f32(0x7fc00000u));
   res = nan_or(xf, v);
   return nan | dom | zero | one;
+}
+
+// The fast path's special cases: those of atan_special and, for atan and asin,
+// the tiny arguments |x| < 2^-13 (zeros and subnormals included), whose
+// results round to x itself: atan x lies within x^2/3 < 2^-27.6 of x below x
+// (relative), asin x within x^2/6 above it, and half the spacing of the
+// binary32 numbers next to x is at least 2^-25 |x| on either side (and the
+// deviation is far below half the subnormal quantum for subnormal x).
+template <int KIND>
+__device__ __forceinline__ bool atan_special_fast(float xf, float& res) {
+  bool spc = atan_special(xf, KIND, res);
+  if (KIND != ATANK_ACOS) {
+    const bool tiny = fabsf(xf) < 0x1p-13f;
+    res = tiny ? xf : res;
+    spc |= tiny;
+  }
+  return spc;
 }
 
 template <int KIND>
@@ -111,9 +132,9 @@ __device__ __forceinline__ float atan_fast(float xf, const AtanTab& tb, bool& ok
       yh = p.hi + (p.lo + ((neg ? PI_LO : 0.0) + (neg ? -lo : lo)));
     }
   }
-  float res = round_f32_fast<ATAN_LOG2E>(yh, ok);
+  float res = round_f32_bits<ATAN_TEST_E>(yh, ok);
   float sp;
-  if (atan_special(xf, KIND, sp)) {
+  if (atan_special_fast<KIND>(xf, sp)) {
     res = sp;
     ok = true;
   }

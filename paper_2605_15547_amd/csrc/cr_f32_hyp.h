@@ -36,8 +36,14 @@ __device__ __forceinline__ double exp_core_fast(float af, double a, const ExpTab
 }
 
 // Fast-path error: expm1/exp carry <= 4 ulps; the division (div_fast, within
-// 2 ulps) and the sums add <= 4; the test uses 32 ulps.
-constexpr int HYP_LOG2E = 5;
+// 2 ulps) and the sums add <= 4: 8 ulps of y, 16 of yh when yh falls just
+// below a power of two.  The bit test of cr_round.h rejects yh within 32 ulps
+// of the midpoint pattern (sound below 33 ulps).  It needs results that round
+// to normal binary32 numbers or overflow: the tiny arguments of sinh and tanh,
+// whose results could be subnormal, are special cases of the fast path
+// (hyp_special_fast); cosh is at least 1; results of 2^128 and above round to
+// infinity on either side of the test.
+constexpr unsigned HYP_TEST_E = 32;
 
 // Branch-free: res is always written (meaningful only when true is returned).
 __device__ __forceinline__ bool hyp_special(float xf, int kind, float& res) {
@@ -65,13 +71,30 @@ __device__ __forceinline__ double hyp_value_fast(float xf, const ExpTab& tb) {
   }
 }
 
+// The fast path's special cases: those of hyp_special and, for sinh and tanh,
+// the tiny arguments |x| < 2^-13 (zeros and subnormals included), whose
+// results round to x itself: sinh x lies within x^2/6 < 2^-28.6 of x above x
+// (relative), tanh x within x^2/3 < 2^-27.6 below it, and half the spacing of
+// the binary32 numbers next to x is at least 2^-25 |x| on either side (and the
+// deviation is far below half the subnormal quantum for subnormal x).
+template <int KIND>
+__device__ __forceinline__ bool hyp_special_fast(float xf, float& res) {
+  bool spc = hyp_special(xf, KIND, res);
+  if (KIND != HYPK_COSH) {
+    const bool tiny = fabsf(xf) < 0x1p-13f;
+    res = tiny ? xf : res;
+    spc |= tiny;
+  }
+  return spc;
+}
+
 template <int KIND>
 __device__ __forceinline__ float hyp_fast(float xf, const ExpTab& tb, bool& ok) {
   double y = hyp_value_fast<KIND>(xf, tb);
   if (KIND != HYPK_COSH && xf < 0.0f) y = -y;
-  float res = round_f32_fast<HYP_LOG2E>(y, ok);
+  float res = round_f32_bits<HYP_TEST_E>(y, ok);
   float sp;
-  if (hyp_special(xf, KIND, sp)) {
+  if (hyp_special_fast<KIND>(xf, sp)) {
     res = sp;
     ok = true;
   }

@@ -108,10 +108,13 @@ __device__ __forceinline__ Reduced payne_hanek(uint32_t ax, const unsigned* w) {
 // fraction bits of f (bits 153..90 of P) come out low by at most one unit of
 // 2^-64 (the high word R.fhi only; R.flo is not formed).
 __device__ __forceinline__ Reduced payne_hanek_fast(uint32_t ax, const unsigned* w) {
-  int E = (int)(ax >> 23) - 150;
-  E = E < -60 ? -60 : (E > 105 ? 105 : E);
+  // the window of payne_hanek from the exponent field directly: with the
+  // field clamped below at 90 (E = field - 150 >= -60; the field is at most
+  // 255, so the upper clamp never applies), the window starts at
+  // sp = field - 88, so b = ((field - 57) >> 5) - 1 and c = (88 - field) mod 32
+  const int fe = max((int)(ax >> 23), 90);
+  const Window win = {((fe - 57) >> 5) - 1, (unsigned)(88 - fe)};  // c: low 5 bits used
   uint32_t M = (ax & 0x007fffffu) | 0x00800000u;
-  const Window win = window_of(E - 2 + 64);
   const unsigned* t = w + win.b;
   uint32_t W0 = window_word(t[0], t[1], win.c);
   uint32_t W1 = window_word(t[1], t[2], win.c);
@@ -123,7 +126,9 @@ __device__ __forceinline__ Reduced payne_hanek_fast(uint32_t ax, const unsigned*
   a = (uint64_t)M * W0 + (a >> 32);
   uint32_t p4 = (uint32_t)a;
   Reduced R;
-  R.q = (int)((((p4 >> 25) + 1) >> 1) & 63);
+  // k mod 64 = (bits 159..153 of P, plus 1) >> 1: the same as (p4 + 2^25) >> 26,
+  // where a carry out of bit 31 would only add 64
+  R.q = (int)((p4 + 0x02000000u) >> 26);
   R.fhi = (long long)(((uint64_t)funnel(p4, p3, 26) << 32) | funnel(p3, p2, 26));
   R.flo = 0;
   return R;
