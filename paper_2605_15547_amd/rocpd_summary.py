@@ -6,6 +6,7 @@ the same workload into HBM bytes per launch.  Usage:
   python -m paper_2605_15547_amd.rocpd_summary traffic <fetch.db> <write.db> <copy_bytes>
          <elems_per_launch> <source_hash>
   python -m paper_2605_15547_amd.rocpd_summary valu <valu.db> <elems_per_launch> <source_hash>
+  python -m paper_2605_15547_amd.rocpd_summary valu_table <counter.txt> <stats.txt>
 traffic calibrates both counters on the largest dispatch of the runtime's
 plain copy kernel (copy_bytes read and written) and prints the text summary,
 then one JSON line (the content of profiles/traffic.json).  valu reads a run
@@ -13,7 +14,14 @@ with SQ_INSTS_VALU and GRBM_GUI_ACTIVE and prints, per map kernel of
 elems_per_launch elements, VALU instructions per element and the fraction of
 the issue rate used (a CU issues one wave-level VALU instruction per cycle;
 GRBM_GUI_ACTIVE sums the 8 XCDs' busy cycles), then one JSON line (the
-content of profiles/valu.json).
+content of profiles/valu.json).  valu_table turns the text printed by
+"counter" for a SQ_INSTS_VALU + GRBM_GUI_ACTIVE run of bench.py's other
+workloads, and the text printed by "stats" for a kernel trace of the same
+workloads, into VALU instructions per element, issue-rate fraction and average
+duration per kernel; elements per dispatch follow bench.py's workloads (2^26
+binary32 map elements, 2^24 binary64 and complex, 2^20 samples x 256 outputs
+for the DFT, each function's share of the 4096-request batch for the batch
+kernels).
 """
 import json
 import re
@@ -141,9 +149,79 @@ def valu(db, elems, source_hash):
                       "valu_per_elem": out}))
 
 
+def _parse_rows(path, ncols):
+    """(kernel, [last ncols fields]) of a text table printed above"""
+    rows = []
+    for line in open(path):
+        f = line.split()
+        if len(f) < ncols + 1 or f[0] == "kernel":
+            continue
+        try:
+            vals = [float(v) for v in f[-ncols:]]
+        except ValueError:
+            continue
+        rows.append((line[:line.rfind(f[-ncols])].split("  ")[0].strip(), vals, f))
+    return rows
+
+
+def _batch_elems():
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from paper_2605_15547_amd import inputs
+    funcs, lens, _ = inputs.batch_requests()
+    tot = defaultdict(int)
+    for f, n in zip(funcs, lens):
+        tot[f] += int(n)
+    return tot
+
+
+def elems_of(kernel, batch):
+    """elements per dispatch of bench.py's workloads, by kernel"""
+    m = re.match(r"(k_\w+)(?:<\S+>)? \((.+)\)$", kernel)
+    if not m:
+        return 268435456 if kernel == "k_dft" else None
+    k, what = m.group(1), m.group(2)
+    if k in ("k_map_f32", "k_map_sincos", "k_ref32"):
+        return 1 << 26
+    if k in ("k_map_f64", "k_complex", "k_ref64"):
+        return 1 << 24
+    if k in ("k_tiles", "k_tiles_sincos"):
+        return batch.get(what.split()[0])
+    return None
+
+
+def valu_table(counter_txt, stats_txt):
+    batch = _batch_elems()
+    cnt = defaultdict(dict)
+    for line in open(counter_txt):
+        m = re.match(r"(.+?)\s+(SQ_\w+|GRBM_\w+)\s+(\d+)\s+([\d.]+)\s*$", line)
+        if m:
+            cnt[m.group(1).strip()][m.group(2)] = float(m.group(4))
+    ns = {}
+    for line in open(stats_txt):
+        m = re.match(r"(.+?)\s+(\d+)\s+(\d+)\s+([\d.]+)\s+(\d+)\s+(\d+)\s*$", line)
+        if m:
+            ns[m.group(1).strip()] = float(m.group(4))
+    print("%-46s %10s %10s %11s %10s" % ("kernel", "elements", "VALU/elem", "issue_util",
+                                         "avg_ns"))
+    for k in sorted(cnt):
+        c = cnt[k]
+        n = elems_of(k, batch)
+        if not n or "SQ_INSTS_VALU" not in c:
+            continue
+        vpe = c["SQ_INSTS_VALU"] * 64.0 / n
+        util = c["SQ_INSTS_VALU"] / (256.0 * c["GRBM_GUI_ACTIVE"] / 8.0) \
+            if c.get("GRBM_GUI_ACTIVE") else None
+        print("%-46s %10d %10.1f %11s %10s" % (k, n, vpe,
+                                               "-" if util is None else "%.1f%%" % (100 * util),
+                                               "%.0f" % ns[k] if k in ns else "-"))
+
+
 if __name__ == "__main__":
     mode, path = sys.argv[1], sys.argv[2]
-    if mode == "valu":
+    if mode == "valu_table":
+        valu_table(path, sys.argv[3])
+    elif mode == "valu":
         valu(sqlite3.connect(path), int(sys.argv[3]), sys.argv[4])
     elif mode == "traffic":
         traffic(sqlite3.connect(path), sqlite3.connect(sys.argv[3]), int(sys.argv[4]),
