@@ -7,6 +7,7 @@ the same workload into HBM bytes per launch.  Usage:
          <elems_per_launch> <source_hash>
   python -m paper_2605_15547_amd.rocpd_summary valu <valu.db> <elems_per_launch> <source_hash>
   python -m paper_2605_15547_amd.rocpd_summary valu_table <counter.txt> <stats.txt>
+  python -m paper_2605_15547_amd.rocpd_summary flops_table <counter.txt>... <stats.txt>...
 traffic calibrates both counters on the largest dispatch of the runtime's
 plain copy kernel (copy_bytes read and written) and prints the text summary,
 then one JSON line (the content of profiles/traffic.json).  valu reads a run
@@ -21,9 +22,14 @@ workloads, into VALU instructions per element, issue-rate fraction and average
 duration per kernel; elements per dispatch follow bench.py's workloads (2^26
 binary32 map elements, 2^24 binary64 and complex, 2^20 samples x 256 outputs
 for the DFT, each function's share of the 4096-request batch for the batch
-kernels).
+kernels).  flops_table does the same for runs of the per-type VALU counters
+(SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_{F32,F64}, _INT32, _INT64, _CVT): the
+instruction mix per element and the binary64 and binary32 floating-point rates
+(an FMA counts two operations, every lane of a wave-level instruction one)
+against MI355X's vector peaks, 78.6 TFLOP/s binary64 and 157.3 TFLOP/s binary32.
 """
 import json
+import os
 import re
 import sqlite3
 import sys
@@ -217,9 +223,61 @@ def valu_table(counter_txt, stats_txt):
                                                "%.0f" % ns[k] if k in ns else "-"))
 
 
+def _load_counters(paths):
+    cnt = defaultdict(dict)
+    for path in paths:
+        for line in open(path):
+            m = re.match(r"(.+?)\s+(SQ_\w+|GRBM_\w+)\s+(\d+)\s+([\d.]+)\s*$", line)
+            if m:
+                cnt[m.group(1).strip()][m.group(2)] = float(m.group(4))
+    return cnt
+
+
+def _load_ns(paths):
+    ns = {}
+    for path in paths:
+        for line in open(path):
+            m = re.match(r"(.+?)\s+(\d+)\s+(\d+)\s+([\d.]+)\s+(\d+)\s+(\d+)\s*$", line)
+            if m:
+                ns[m.group(1).strip()] = float(m.group(4))
+    return ns
+
+
+FP64_PEAK, FP32_PEAK = 78.6, 157.3  # TFLOP/s, MI355X vector (non-matrix) peaks
+
+
+def flops_table(counter_txts, stats_txts):
+    batch = _batch_elems()
+    cnt, ns = _load_counters(counter_txts), _load_ns(stats_txts)
+    types = ["FMA_F64", "ADD_F64", "MUL_F64", "TRANS_F64", "FMA_F32", "ADD_F32", "MUL_F32",
+             "TRANS_F32", "INT32", "INT64", "CVT"]
+    print("instructions per element by type (wave-level counts x 64 / elements), and the")
+    print("floating-point rates: TF64 = (2 FMA_F64 + ADD_F64 + MUL_F64) x 64 lanes / avg_ns,")
+    print("TF32 likewise for binary32, against %.1f and %.1f TFLOP/s" % (FP64_PEAK, FP32_PEAK))
+    print("%-40s" % "kernel" + "".join("%8s" % t.replace("_F", ".") for t in types)
+          + "%8s %6s %8s %6s" % ("TF64", "%pk", "TF32", "%pk"))
+    for k in sorted(cnt):
+        c = cnt[k]
+        n = elems_of(k, batch)
+        if not n or "SQ_INSTS_VALU_FMA_F64" not in c:
+            continue
+        per = {t: c.get("SQ_INSTS_VALU_" + t, 0.0) * 64.0 / n for t in types}
+        row = "%-40s" % k[:40] + "".join("%8.1f" % per[t] for t in types)
+        if k in ns:
+            f64 = (2 * per["FMA_F64"] + per["ADD_F64"] + per["MUL_F64"]) * n / ns[k] / 1e3
+            f32 = (2 * per["FMA_F32"] + per["ADD_F32"] + per["MUL_F32"]) * n / ns[k] / 1e3
+            row += "%8.2f %5.1f%% %8.2f %5.1f%%" % (f64, 100 * f64 / FP64_PEAK, f32,
+                                                    100 * f32 / FP32_PEAK)
+        print(row)
+
+
 if __name__ == "__main__":
     mode, path = sys.argv[1], sys.argv[2]
-    if mode == "valu_table":
+    if mode == "flops_table":
+        args = sys.argv[2:]
+        flops_table([a for a in args if "stats" not in os.path.basename(a)],
+                    [a for a in args if "stats" in os.path.basename(a)])
+    elif mode == "valu_table":
         valu_table(path, sys.argv[3])
     elif mode == "valu":
         valu(sqlite3.connect(path), int(sys.argv[3]), sys.argv[4])
