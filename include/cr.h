@@ -195,7 +195,7 @@ int cr_batch_plan_create(const cr_request *reqs, int32_t num, unsigned flags,
                          cr_batch_plan **plan);
 /* Launch the plan's graph on the stream (asynchronous, stream-ordered).  The
  * graph holds one persistent kernel per (implementation, function) present,
- * each over its own contiguous range of 2048-element tiles (requests are
+ * each over its own contiguous range of 4096-element tiles (requests are
  * sorted by implementation and function when the plan is made), spread over
  * four parallel branches that join before the launch completes. */
 int cr_batch_plan_launch(cr_batch_plan *plan, void *stream);
@@ -215,7 +215,7 @@ int cr_eval_batch(const cr_request *reqs, int32_t num, void *stream);
  * allocations.  The call makes no hipMalloc/hipFree or other allocating
  * device call.  The scratch holds at most CR_NOALLOC_MAX_REQUESTS requests and
  * CR_NOALLOC_MAX_TILES tiles, where a request of n elements takes
- * ceil(n / 2048) tiles (about 10^9 elements in all); larger batches return
+ * ceil(n / 4096) tiles (about 2 10^9 elements in all); larger batches return
  * CR_E_SCRATCH before anything is copied or launched.  Each device holds one
  * scratch (about 8.4 MiB, kept until the process ends) shared by every call
  * on that device: calls on one stream are ordered, but calls that overlap in

@@ -63,8 +63,19 @@ struct DevStats {
 #define CR_BLOCKS_PER_CU 16
 #endif
 constexpr int BLOCK = 256;
-constexpr int TILE_U = CR_TILE_U;           // float4 vectors per thread per tile
-constexpr int TILE = BLOCK * 4 * TILE_U;    // 2048 elements per tile
+constexpr int TILE_U = CR_TILE_U;           // float4 vectors per thread per tile (sincosf)
+// Batch tiles: BATCH_U float4 vectors per thread, TILE elements per tile.
+// Measured on the 4096-request batch, binary64-internal: 1 -> 463, 2 -> 493,
+// 4 -> 496-503, 8 -> 493-499 Gelem/s (larger tiles mean fewer tile-table
+// reads and queue checks per element, smaller ones a shorter tail).  The
+// binary32-only batch ran at 321-327 or 363-368 Gelem/s depending on the
+// build even where its kernels were instruction for instruction the same,
+// so it did not decide the size.
+#ifndef CR_BATCH_U
+#define CR_BATCH_U 4
+#endif
+constexpr int BATCH_U = CR_BATCH_U;
+constexpr int TILE = BLOCK * 4 * BATCH_U;   // 4096 elements per tile
 constexpr int QCAP = 512;                   // deferred elements held in LDS
 constexpr int QCHECK = 8;                   // tiles between two looks at the queue
 constexpr int QFLUSH = QCAP / 2;            // flush when the queue is fuller than this
@@ -1188,7 +1199,7 @@ __global__ void __launch_bounds__(BLOCK)
 
 // ------------------------------------------------------------ ragged batch
 // One persistent kernel evaluates a whole plan: a request table (function,
-// pointers, length) and a tile table (request, start, count; tiles of 2048
+// pointers, length) and a tile table (request, start, count; tiles of TILE
 // elements).  Each workgroup walks a contiguous range of tiles; requests are
 // ordered by function when the plan is built, so consecutive tiles mostly
 // share a function and its LDS table, which is reloaded only when the
@@ -1263,7 +1274,7 @@ __device__ __forceinline__ void batch_tile(BReq R, BTile T, const typename Op::T
   if (R.aligned) {
     const int n4 = cnt >> 2;
 #pragma unroll
-    for (int u = 0; u < TILE_U; u++) {
+    for (int u = 0; u < BATCH_U; u++) {
       int i = threadIdx.x + u * BLOCK;
       if (i < n4) {
         float4 v = ld_stream(reinterpret_cast<const float4*>(in) + i);
@@ -1329,7 +1340,7 @@ __device__ __forceinline__ void batch_tile_sincos(BReq R, BTile T, const typenam
   if (R.aligned) {  // input, sine block and cosine block 16-byte aligned
     const int n4 = cnt >> 2;
 #pragma unroll
-    for (int u = 0; u < TILE_U; u++) {
+    for (int u = 0; u < BATCH_U; u++) {
       int i = threadIdx.x + u * BLOCK;
       if (i < n4) {
         float4 v = ld_stream(reinterpret_cast<const float4*>(in) + i), cv;

@@ -87,7 +87,8 @@ def test_noalloc_rejects_oversize_batches():
     L = crmath.lib()
     big = (crmath.Request * (crmath.NOALLOC_MAX_REQUESTS + 1))()
     assert L.cr_eval_batch_noalloc(big, len(big), None) == -11
-    # one request per 2^30 elements: 2^30 / 2048 = 2^19 tiles each, two of them
+    # two requests of 2^31 - 1 elements: 2^19 tiles of 4096 elements each, twice
+    # the 2^19 tiles the scratch holds
     x = torch.empty(4, device="cuda")
     y = torch.empty(4, device="cuda")
     arr = (crmath.Request * 2)()
