@@ -101,7 +101,9 @@ def hard_set(func):
     (tests/golden/hard/<func>.u32, written by tests/golden/make_hard_sets.py)."""
     path = os.path.join(GOLDEN, "hard", func + (".u64" if func in F64_FUNCS else ".u32"))
     if not os.path.exists(path):
-        return None
+        # the workloads' hard-input share depends on it: fail rather than
+        # silently generating a different workload
+        raise FileNotFoundError("hard set of %s missing: %s" % (func, path))
     dt = np.uint64 if func in F64_FUNCS else np.uint32
     a = np.fromfile(path, dtype=dt)
     return a.view(np.float64 if func in F64_FUNCS else np.float32)
@@ -157,7 +159,7 @@ def explog_family(func, n, seed=None):
     raw = f32_bits(st.u32(n))
     x = np.where((cat >= 90) & (cat < 95), raw, x)
     hs = hard_set(func)
-    if hs is not None and hs.size:
+    if hs.size:
         pick = hs[st.below(n, hs.size)]
         x = np.where(cat >= 95, pick, x)
     return np.ascontiguousarray(x, dtype=np.float32)
@@ -198,7 +200,7 @@ def workload_f64(func, n, seed=None):
         raise ValueError(func)
     hs = hard_set(func)
     k = max(1, int(round(n * 1e-4))) if n >= 1000 else 0
-    if hs is not None and hs.size and k:
+    if hs.size and k:
         pos = st.below(k, n)
         x[pos] = hs[st.below(k, hs.size)]
     return np.ascontiguousarray(x, dtype=np.float64)
