@@ -314,12 +314,19 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """sha256 (first 16 hex digits) of the kernel sources csrc/cr_* with their
+    comments removed: a change of code invalidates the committed counter
+    summaries, a change of comments does not."""
     import glob
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_2605_15547_amd", "csrc", "cr_*"))):
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update(text.encode())
     return h.hexdigest()[:16]
 
 

@@ -65,12 +65,10 @@ struct DevStats {
 constexpr int BLOCK = 256;
 constexpr int TILE_U = CR_TILE_U;           // float4 vectors per thread per tile (sincosf)
 // Batch tiles: BATCH_U float4 vectors per thread, TILE elements per tile.
-// Measured on the 4096-request batch, binary64-internal: 1 -> 463, 2 -> 493,
-// 4 -> 496-503, 8 -> 493-499 Gelem/s (larger tiles mean fewer tile-table
-// reads and queue checks per element, smaller ones a shorter tail).  The
-// binary32-only batch ran at 321-327 or 363-368 Gelem/s depending on the
-// build even where its kernels were instruction for instruction the same,
-// so it did not decide the size.
+// Measured on the 4096-request batch (three alternating runs per build),
+// 4096-element tiles against 2048: +0.9% binary64-internal, +1.6%
+// binary32-only, within the run-to-run spread (larger tiles mean fewer
+// tile-table reads and queue checks per element, smaller ones a shorter tail).
 #ifndef CR_BATCH_U
 #define CR_BATCH_U 4
 #endif
