@@ -394,8 +394,17 @@ __device__ __forceinline__ double log64_fast(double x, const Log64Tab& tb, bool&
   // log1p t = t - t^2/2 + t^3/3 + t^4 S(t)
   dd t2 = two_prod(t.hi, t.hi);
   t2.lo = fma(2.0 * t.hi, t.lo, t2.lo);
-  dd t3 = dd_mul(t2, t);
-  dd b3 = dd_mul(t3, dd{THIRD_HI, THIRD_LO});
+  // t^3/3 as an unnormalised double-double (dd_add_ord below renormalises):
+  // t2.hi t.hi exactly by TwoProd, the cross terms t2.hi t.lo + t2.lo t.hi
+  // added by fmas (t2.lo t.lo, below 2^-106 |t|^3, dropped), then the same
+  // with 1/3 = THIRD_HI + THIRD_LO: within 10u^2 relative, as two dd_mul
+  dd b3;
+  {
+    const dd p3 = two_prod(t2.hi, t.hi);
+    const double p3l = fma(t2.lo, t.hi, fma(t2.hi, t.lo, p3.lo));
+    b3 = two_prod(p3.hi, THIRD_HI);
+    b3.lo = fma(p3l, THIRD_HI, fma(p3.hi, THIRD_LO, b3.lo));
+  }
   double sp = LOG64_S[LOG64_S_DEG];
 #pragma unroll
   for (int i = LOG64_S_DEG - 1; i >= 0; i--) sp = fma(sp, t.hi, LOG64_S[i]);
