@@ -50,6 +50,25 @@ def bytes_per_elem(func):
     return 16 if func in F64 else (12 if func == "sincosf" else 8)
 
 
+def sample_sclk(result):
+    """The shader clock while the settle phase keeps the GPU busy: one
+    `rocm-smi --showclocks` (a child process), its sclk lines parsed (MHz; the
+    largest if several GPUs are listed).  Stores the value, or None and why."""
+    import re
+    import subprocess
+    try:
+        out = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True,
+                             timeout=15).stdout
+        mhz = [int(m) for m in re.findall(r"sclk clock level:\s*\d+:\s*\((\d+)\s*Mhz\)", out,
+                                          flags=re.I)]
+        result["sclk_mhz"] = max(mhz) if mhz else None
+        if not mhz:
+            result["why"] = "no sclk line in rocm-smi --showclocks"
+    except (OSError, subprocess.SubprocessError) as e:
+        result["sclk_mhz"] = None
+        result["why"] = str(e)[:120]
+
+
 def settle(fn, seconds, torch):
     """Untimed launches for `seconds` so the clocks settle under this load."""
     t0 = time.perf_counter()
@@ -507,8 +526,17 @@ def main():
 
     # let the clocks settle under this load before the warm-up steps (the first
     # ~100 ms of work run at lower clocks)
+    # the shader clock is sampled once, half-way through, while the loop keeps
+    # the GPU busy (the loop runs until the sample is in)
+    import threading
+    sclk = {"sclk_mhz": None, "when": "rocm-smi --showclocks during the settle launches"}
+    sampler = threading.Thread(target=lambda: (time.sleep(min(0.5, a.settle / 2)),
+                                               sample_sclk(sclk)), daemon=True)
     t_settle = time.perf_counter()
-    while time.perf_counter() - t_settle < a.settle:
+    if a.settle > 0:
+        sampler.start()
+    while time.perf_counter() - t_settle < a.settle or (a.settle > 0 and sampler.is_alive()
+                                                       and time.perf_counter() - t_settle < 20):
         for f in funcs:
             run(f)
         torch.cuda.synchronize()
@@ -557,6 +585,12 @@ def main():
         roof["valu"] = {"instr_per_elem": vpe, "achieved_lane_instr_s": round(rate / 1e12, 2),
                         "peak_lane_instr_s": round(VALU_PEAK / 1e12, 2), "unit": "T/s",
                         "frac": round(rate / VALU_PEAK, 4)}
+        # the same against the issue rate at the shader clock seen under this
+        # load (sampled during the settle phase), when it was read
+        if sclk.get("sclk_mhz"):
+            at = 256 * 64 * sclk["sclk_mhz"] * 1e6
+            roof["valu"]["frac_at_measured_clock"] = round(rate / at, 4)
+            roof["valu"]["measured_clock_mhz"] = sclk["sclk_mhz"]
     else:
         roof["valu"] = None
 
@@ -634,6 +668,7 @@ def main():
            "roofline": roof, "cpu_baseline": cpu, "parity_vs_oracle": parity,
            "other_workloads": extra}
     rec["split_f32_vs_f64"] = split_vs_f64(per, extra, n)
+    rec["clock_under_load"] = sclk
     if copy_ms is not None:
         rec["copy_ref"] = {"ms": round(copy_ms, 4), "bytes": 8 * n,
                            "gb_s": round(8 * n / (copy_ms * 1e-3) / 1e9, 1)}
