@@ -14,7 +14,8 @@ time, measured with HIP events on the stream it runs on.  cpu_baseline times
 the CPU oracle (oracle/) on a bounded sample of the same inputs.
 
 other_workloads (left out with --headline-only) reports, outside the headline
-value: the trig/inverse-trig/hyperbolic family at the same size, binary64
+value: expf on its 2^20 + 64-element correctness set (launch-bound: the median
+launch), the trig/inverse-trig/hyperbolic family at the same size, binary64
 exp/log/exp2 on 2^24 inputs each (exp2 uniform in [-20, 20], the paper's
 range), the paper's GPU metric (correctly rounded over the platform's ~1-ulp
 library functions for expf, logf, sincosf, exp, log, exp2),
@@ -43,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK = 256 * 64 * 2.4e9  # lane-instructions/s: one wave64 VALU instruction per CU per cycle
 FAMILY = ["expf", "exp2f", "exp10f", "expm1f", "logf", "log2f", "log10f", "log1pf", "rsqrtf"]
 TRIG = ["sinf", "cosf", "sincosf", "tanf", "asinf", "acosf", "atanf", "sinhf", "coshf", "tanhf"]
-OTHER_LEGS = ("trig", "binary64", "vsulp", "complex", "dft", "batch", "split")
+OTHER_LEGS = ("correctness", "trig", "binary64", "vsulp", "complex", "dft", "batch", "split")
 
 
 def bytes_per_elem(func):
@@ -283,6 +284,41 @@ def bench_dft(torch, crmath, inputs, n, m, steps, warmup, stream):
          "what": "terms x[j] (cos t - i sin t), t = RN32(w_k j), per second; sincosf "
                  "correctly rounded, double-double sums"}
     log("bench: dft", r)
+    return r
+
+
+def bench_correctness_set(torch, crmath, inputs, steps, warmup, stream):
+    """expf on its correctness set (64 specials and edges, then 2^20 values
+    uniform in [-103.9, 88.7]), binary64-internal: 8.4 MB, about a
+    microsecond of HBM time, so the launch dominates.  Per-launch events; the
+    median launch is reported."""
+    x = inputs.expf_correctness_set()
+    xt = torch.from_numpy(x).cuda()
+    out = torch.empty_like(xt)
+    sp = crmath._stream_ptr(stream)
+    n = x.size
+
+    def run():
+        crmath.eval_ptr("expf", xt.data_ptr(), out.data_ptr(), n, 1, 0, sp)
+
+    settle(run, 0.2, torch)
+    for _ in range(warmup):
+        run()
+    reps = max(steps, 20)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    torch.cuda.synchronize()
+    for e0, e1 in evs:
+        e0.record(stream)
+        run()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = sorted(e0.elapsed_time(e1) for e0, e1 in evs)[reps // 2]
+    r = {"func": "expf", "impl": "f64_internal", "elements": int(n), "us_per_launch": round(ms * 1e3, 2),
+         "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+         "hbm_frac": round(8 * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+         "note": "launch-bound (about 1 us of HBM time at 8 TB/s); not a roofline figure"}
+    log("bench: correctness set", r)
     return r
 
 
@@ -619,6 +655,9 @@ def main():
         del xs, outs
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
+        if "correctness" in legs:
+            extra["expf_correctness_set"] = bench_correctness_set(torch, crmath, inputs, a.steps,
+                                                                  a.warmup, stream)
         if "trig" in legs:
             extra["trig_hyperbolic_family"] = bench_family(
                 torch, crmath, inputs, TRIG, n, a.impl, a.steps, a.warmup, stream)
