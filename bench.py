@@ -412,6 +412,20 @@ def measured_valu(func, n):
     return t["valu_per_elem"].get(func)
 
 
+def measured_flops(func, n):
+    """binary64 and binary32 floating-point operations per element of func's
+    kernel from the committed per-type VALU counter run, or None when the
+    kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "flops.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != kernel_source_hash() or t.get("elems_per_launch") != n:
+        return None
+    return t["flops_per_elem"].get(func)
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -629,6 +643,20 @@ def main():
             roof["valu"]["measured_clock_mhz"] = sclk["sclk_mhz"]
     else:
         roof["valu"] = None
+    # the same kernel's floating-point rate against the vector peaks (binary64
+    # 78.6, binary32 157.3 TFLOP/s), from the committed per-type counter run
+    fl = measured_flops(dom, n)
+    if fl is not None:
+        eps = n / (per[dom]["ms"] * 1e-3)
+        roof["flops"] = {"fp64_per_elem": fl["fp64_per_elem"],
+                         "fp64_tflop_s": round(fl["fp64_per_elem"] * eps / 1e12, 2),
+                         "fp64_peak": 78.6, "fp64_frac": round(fl["fp64_per_elem"] * eps / 78.6e12, 4),
+                         "fp32_per_elem": fl["fp32_per_elem"],
+                         "fp32_tflop_s": round(fl["fp32_per_elem"] * eps / 1e12, 2),
+                         "fp32_peak": 157.3,
+                         "fp32_frac": round(fl["fp32_per_elem"] * eps / 157.3e12, 4)}
+    else:
+        roof["flops"] = None
 
     # the leading outputs of the last timed step, for the check against the
     # oracle results the cpu_baseline leg computes

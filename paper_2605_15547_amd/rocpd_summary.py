@@ -8,6 +8,7 @@ the same workload into HBM bytes per launch.  Usage:
   python -m paper_2605_15547_amd.rocpd_summary valu <valu.db> <elems_per_launch> <source_hash>
   python -m paper_2605_15547_amd.rocpd_summary valu_table <counter.txt> <stats.txt>
   python -m paper_2605_15547_amd.rocpd_summary flops_table <counter.txt>... <stats.txt>...
+  python -m paper_2605_15547_amd.rocpd_summary flops_json <counter.txt> <elems_per_launch> <source_hash>
 traffic calibrates both counters on the largest dispatch of the runtime's
 plain copy kernel (copy_bytes read and written) and prints the text summary,
 then one JSON line (the content of profiles/traffic.json).  valu reads a run
@@ -27,6 +28,9 @@ kernels).  flops_table does the same for runs of the per-type VALU counters
 instruction mix per element and the binary64 and binary32 floating-point rates
 (an FMA counts two operations, every lane of a wave-level instruction one)
 against MI355X's vector peaks, 78.6 TFLOP/s binary64 and 157.3 TFLOP/s binary32.
+flops_json prints, per map kernel of elems_per_launch elements, the binary64
+and binary32 floating-point operations per element (the content of
+profiles/flops.json, read by bench.py for the headline's roofline).
 """
 import json
 import os
@@ -271,9 +275,26 @@ def flops_table(counter_txts, stats_txts):
         print(row)
 
 
+def flops_json(counter_txt, elems, source_hash):
+    cnt = _load_counters([counter_txt])
+    out = {}
+    for k, c in cnt.items():
+        m = re.search(r"k_map_f32<(\w+(?:<\d+>)?)>", k)
+        if not m or m.group(1) not in FUNCS or "SQ_INSTS_VALU_FMA_F64" not in c:
+            continue
+        g = lambda t: c.get("SQ_INSTS_VALU_" + t, 0.0) * 64.0 / elems
+        out[FUNCS[m.group(1)]] = {
+            "fp64_per_elem": round(2 * g("FMA_F64") + g("ADD_F64") + g("MUL_F64"), 3),
+            "fp32_per_elem": round(2 * g("FMA_F32") + g("ADD_F32") + g("MUL_F32"), 3)}
+    print(json.dumps({"source_hash": source_hash, "elems_per_launch": elems,
+                      "flops_per_elem": out}))
+
+
 if __name__ == "__main__":
     mode, path = sys.argv[1], sys.argv[2]
-    if mode == "flops_table":
+    if mode == "flops_json":
+        flops_json(path, int(sys.argv[3]), sys.argv[4])
+    elif mode == "flops_table":
         args = sys.argv[2:]
         flops_table([a for a in args if "stats" not in os.path.basename(a)],
                     [a for a in args if "stats" in os.path.basename(a)])
