@@ -370,8 +370,9 @@ def log(*a):
 
 def kernel_source_hash():
     """sha256 (first 16 hex digits) of the kernel sources csrc/cr_* with their
-    comments removed: a change of code invalidates the committed counter
-    summaries, a change of comments does not."""
+    comments removed and whitespace runs collapsed: a change of code
+    invalidates the committed counter summaries, a change of comments or
+    layout does not."""
     import glob
     import hashlib
     import re
@@ -379,9 +380,9 @@ def kernel_source_hash():
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_2605_15547_amd", "csrc", "cr_*"))):
         with open(f, encoding="utf-8") as fh:
             text = fh.read()
-        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        text = re.sub(r"//[^\n]*", "", text)
-        h.update(text.encode())
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())  # whitespace runs as one space
     return h.hexdigest()[:16]
 
 
